@@ -1,0 +1,395 @@
+/*
+ * csrc.h -- C ABI of the MI355X (gfx950) CSRC sparse matrix-vector library.
+ *
+ * The operation (Batista, Ainsworth Jr., Ribeiro, "Parallel structurally-
+ * symmetric sparse matrix-vector products on multi-core processors"):
+ * given an n x n sparse matrix A with a structurally symmetric pattern and a
+ * dense source vector x, compute the destination vector y = A x (Sec. 1), and
+ * the transpose product y = A^T x that the format defines implicitly (Sec. 5).
+ *
+ * Storage (Sec. 2): A = A_D + A_L + A_U.
+ *   ad[n]      diagonal entries a_ii (0 where not stored)
+ *   ia[n+1]    row pointers of the strictly lower part (0-based, ia[0] = 0)
+ *   ja[k]      column indices of the strictly lower part, ascending per row
+ *   al[k]      al[q] = a(i, ja[q]) for q in row i          (A_L by rows)
+ *   au[k]      au[q] = a(ja[q], i), the mirrored upper entry (A_U by columns)
+ * k is the number of stored strictly-lower pairs.  Indices are int32.
+ *
+ * Conventions for every entry point:
+ *   - The return value is a csrc_status; CSRC_OK (0) or a negative code.
+ *     No C++ exception crosses the ABI.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are GPU
+ *     memory of the current HIP device (the library never allocates or frees
+ *     device memory: the caller passes buffers and a workspace).
+ *   - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *     GPU entry points are asynchronous on that stream.
+ *   - n = 0 is a valid no-op.  NaN and Inf propagate under IEEE rules.
+ *   - Entry points are reentrant; a plan is immutable once created and may be
+ *     shared by concurrent calls that use distinct workspaces.
+ */
+#ifndef CSRC_H
+#define CSRC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef enum csrc_status {
+    CSRC_OK = 0,
+    CSRC_ERR_ARG = -1,             /* null pointer, negative size, bad option   */
+    CSRC_ERR_NOT_STRUCT_SYM = -2,  /* pattern of the input is not symmetric      */
+    CSRC_ERR_DUPLICATE = -3,       /* an (i, j) pair stored twice                 */
+    CSRC_ERR_INDEX_RANGE = -4,     /* column index outside [0, n)                 */
+    CSRC_ERR_TOO_LARGE = -5,       /* k or a table does not fit 32-bit indices    */
+    CSRC_ERR_ALIAS = -6,           /* destination overlaps the source             */
+    CSRC_ERR_WORKSPACE = -7,       /* workspace null or smaller than required     */
+    CSRC_ERR_HIP = -8,             /* a HIP runtime call failed                   */
+    CSRC_ERR_UNSUPPORTED = -9,     /* variant cannot run this matrix (e.g. the
+                                      private windows exceed the LDS budget)      */
+    CSRC_ERR_PLAN = -10,           /* plan does not match the matrix or call      */
+    CSRC_ERR_NOMEM = -11           /* host allocation failed                      */
+} csrc_status;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *csrc_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t csrc_version(void);
+
+/* ------------------------------------------------------------ data types */
+typedef enum csrc_dtype {
+    CSRC_F64 = 0,
+    CSRC_F32 = 1,
+    CSRC_BF16 = 2
+} csrc_dtype;
+
+/* ------------------------------------------------- host-side conversion */
+
+/* Flags of csrc_count / csrc_from_csr. */
+#define CSRC_PAD_PATTERN 1  /* add explicit zeros to symmetrise the pattern
+                               instead of failing with CSRC_ERR_NOT_STRUCT_SYM */
+
+/*
+ * csrc_count -- validate a CSR matrix and count its strictly-lower pairs.
+ * (Sec. 2: k = (nnz - n)/2 for a full diagonal; here k counts the stored
+ * strictly-lower entries of the (possibly padded) symmetric pattern.)
+ *   n        order of A (>= 0)
+ *   row_ptr  host, n+1 entries, row_ptr[0] = 0, non-decreasing
+ *   col      host, row_ptr[n] column indices (any order within a row)
+ *   flags    0 or CSRC_PAD_PATTERN
+ *   k_out    host, receives k
+ * Errors: ARG, INDEX_RANGE, DUPLICATE, NOT_STRUCT_SYM, TOO_LARGE (k >= 2^31).
+ */
+int csrc_count(int32_t n, const int64_t *row_ptr, const int32_t *col,
+               int32_t flags, int64_t *k_out);
+
+/*
+ * csrc_from_csr -- split a CSR matrix into CSRC arrays (Sec. 2).
+ * All pointers are host memory owned by the caller.  Outputs: ia[n+1],
+ * ja[k], ad[n], al[k], au[k] with k from csrc_count (same flags).  Within a
+ * row the lower columns are sorted ascending, so the output is canonical.
+ * Same errors as csrc_count.
+ */
+int csrc_from_csr(int32_t n, const int64_t *row_ptr, const int32_t *col,
+                  const double *val, int32_t flags,
+                  int32_t *ia, int32_t *ja, double *ad, double *al, double *au);
+
+/*
+ * csrc_quantize -- round FP64 values to a storage type, host to host.
+ *   dtype CSRC_F32: IEEE round-to-nearest-even; CSRC_BF16: RNE of the FP32
+ *   value to bfloat16 (dst holds uint16 bit patterns); CSRC_F64: copy.
+ */
+int csrc_quantize(int64_t count, const double *src, int32_t dtype, void *dst);
+
+/* ----------------------------------------------------------- matrices */
+
+/* A CSRC matrix resident on the device.  Value arrays hold vdtype. */
+typedef struct csrc_matrix {
+    int32_t n;
+    int32_t vdtype;        /* csrc_dtype of ad, al, au                        */
+    int64_t k;
+    const int32_t *ia;     /* device, n+1 */
+    const int32_t *ja;     /* device, k   */
+    const void *ad;        /* device, n   */
+    const void *al;        /* device, k   */
+    const void *au;        /* device, k   */
+} csrc_matrix;
+
+/*
+ * Vector types.  FP64 storage uses FP64 x and y.  FP32/BF16 storage uses an
+ * FP32 x, accumulates in FP32 and writes y as CSRC_F32 or CSRC_F64
+ * (csrc_plan_opts.ydtype).
+ */
+
+/* ------------------------------------------------------------ variants */
+typedef enum csrc_variant {
+    /* One thread per row; y cleared, then every row sum and every mirrored
+       upper product added with a global atomic.  The plain baseline.        */
+    CSRC_V_PLAIN = 0,
+    /* Row segments of g lanes (csrc_plan_opts.lanes) stream ja/al/au
+       coalesced, reduce the row sum with lane shuffles and add it, and each
+       scattered au*x_i, with global atomics (Sec. 3: atomic primitives).      */
+    CSRC_V_ATOMIC = 1,
+    /* Local buffers (Sec. 3.1) per workgroup: a tile of nnz-balanced rows
+       accumulates its own rows and its out-of-tile targets (its effective
+       range, stored as compact windows) in LDS; pass 2 adds the windows into
+       y in ascending tile order.                                              */
+    CSRC_V_PRIVATE = 2,
+    /* Colourful method (Sec. 3.2): rows grouped into conflict-free colour
+       classes, processed one class per launch with plain stores.            */
+    CSRC_V_COLOR = 3,
+    /* Owner-computes: the workgroup that owns a tile of y also visits the
+       rows above it that scatter into the tile, so every y entry is formed
+       by one workgroup in LDS and stored once; no partials, no atomics.      */
+    CSRC_V_OWNER = 4,
+    CSRC_V_COUNT = 5
+} csrc_variant;
+
+/* Colouring criteria (Sec. 3.2). */
+#define CSRC_COLOR_WRITE_SET 0   /* rows conflict iff their write sets meet   */
+#define CSRC_COLOR_DISTANCE2 1   /* direct or common-neighbour conflicts      */
+
+typedef struct csrc_plan_opts {
+    int32_t variant;          /* csrc_variant                                 */
+    int32_t tile_work;        /* target work per tile, counted as 2 per lower
+                                 pair + 1 per row (nnz-guided, Sec. 3.1);
+                                 0 = default                                  */
+    int32_t lanes;            /* lanes per row segment: 1,2,4,...,64; 0 = auto */
+    int32_t block;            /* threads per workgroup: 64..1024, multiple of
+                                 64; 0 = default                              */
+    int32_t color_criterion;  /* CSRC_COLOR_*                                 */
+    int32_t ydtype;           /* output type for FP32/BF16 storage            */
+    int32_t compensated;      /* 1: compensated (TwoSum) accumulation of
+                                 partial sums in the merge; reduced precision  */
+    int32_t max_rhs;          /* largest r later passed to csrc_spmm (>= 1)   */
+} csrc_plan_opts;
+
+/* Fills opts with the defaults of a variant. */
+int csrc_plan_opts_default(int32_t variant, csrc_plan_opts *opts);
+
+typedef struct csrc_plan csrc_plan;   /* opaque, host-side */
+
+/*
+ * csrc_plan_create -- host-side setup for one matrix and one variant:
+ * nnz-guided tiles (Sec. 3.1), effective-range windows and merge lists,
+ * greedy colour classes (Sec. 3.2).  ia/ja are HOST copies of the matrix
+ * structure.  vdtype is the storage type the plan will be used with.
+ * Errors: ARG, UNSUPPORTED (e.g. windows beyond the LDS budget), NOMEM.
+ */
+int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
+                     int32_t vdtype, const csrc_plan_opts *opts,
+                     csrc_plan **out);
+int csrc_plan_destroy(csrc_plan *plan);
+
+/* Device workspace a plan needs (bytes, 256-byte aligned); 0 for none. */
+int64_t csrc_plan_workspace_bytes(const csrc_plan *plan);
+
+/*
+ * csrc_plan_upload -- copy the plan's tables into the caller's device
+ * workspace (ordered on stream).  Must precede the first product that uses
+ * this workspace; the tables are then read-only, so one upload serves any
+ * number of products.  Errors: WORKSPACE, HIP.
+ */
+int csrc_plan_upload(const csrc_plan *plan, void *workspace, int64_t bytes,
+                     void *stream);
+
+typedef struct csrc_plan_info {
+    int32_t variant;
+    int32_t ntiles;         /* workgroup tiles (0 for PLAIN)                   */
+    int32_t ncolors;        /* colour classes (COLOR)                          */
+    int32_t lanes;
+    int32_t block;
+    int32_t max_tile_rows;
+    int32_t max_window;     /* largest per-tile window / pulled-row count      */
+    int32_t nintervals;     /* window intervals over all tiles                 */
+    int64_t window_slots;   /* partial slots over all tiles (PRIVATE)          */
+    int64_t pulled_rows;    /* rows visited by non-owners (OWNER)              */
+    int64_t lds_bytes;      /* dynamic LDS per workgroup                        */
+    int64_t workspace_bytes;
+} csrc_plan_info;
+
+int csrc_plan_get_info(const csrc_plan *plan, csrc_plan_info *info);
+
+/*
+ * csrc_plan_export -- copy host-side plan tables (for verification):
+ *   what 0: tile boundaries, ntiles+1 int32
+ *   what 1: row colours, n int32 (COLOR)
+ *   what 2: window intervals, 3*nintervals int32 triples
+ *           (tile, first row, row count), ascending by tile then row
+ * count is the capacity of dst in int32 elements; the needed count is
+ * returned in *needed.
+ */
+int csrc_plan_export(const csrc_plan *plan, int32_t what, int32_t *dst,
+                     int64_t count, int64_t *needed);
+
+/* --------------------------------------------------------------- products */
+
+/*
+ * csrc_spmv -- y <- A x (Fig. 2a semantics: y is overwritten, its input
+ * contents are ignored).
+ *   A          matrix descriptor (host struct holding device pointers)
+ *   plan       from csrc_plan_create for this matrix structure
+ *   x, y       device vectors of n elements (types above); y must not
+ *              overlap x (CSRC_ERR_ALIAS)
+ *   workspace  device buffer of csrc_plan_workspace_bytes(plan) bytes that
+ *              holds the uploaded plan tables; NULL allowed when that size
+ *              is 0
+ * Errors: ARG, PLAN, ALIAS, WORKSPACE, HIP (launch failure).
+ */
+int csrc_spmv(const csrc_matrix *A, const csrc_plan *plan, const void *x,
+              void *y, void *workspace, int64_t ws_bytes, void *stream);
+
+/* csrc_spmv_t -- y <- A^T x: the same kernels with al and au exchanged (Sec. 5). */
+int csrc_spmv_t(const csrc_matrix *A, const csrc_plan *plan, const void *x,
+                void *y, void *workspace, int64_t ws_bytes, void *stream);
+
+/*
+ * csrc_spmm / csrc_spmm_t -- Y <- A X (or A^T X) for r right-hand sides.
+ * X and Y are row-major n x r blocks with leading dimensions ldx, ldy >= r
+ * (element (i, c) at X[i*ldx + c]); 1 <= r <= plan max_rhs and r <= 32.
+ * Each stored entry is read once and applied to all r columns.
+ */
+int csrc_spmm(const csrc_matrix *A, const csrc_plan *plan, int32_t r,
+              const void *X, int64_t ldx, void *Y, int64_t ldy,
+              void *workspace, int64_t ws_bytes, void *stream);
+int csrc_spmm_t(const csrc_matrix *A, const csrc_plan *plan, int32_t r,
+                const void *X, int64_t ldx, void *Y, int64_t ldy,
+                void *workspace, int64_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------- batches */
+
+typedef struct csrc_batch_plan csrc_batch_plan;   /* opaque, host-side */
+
+typedef struct csrc_batch_opts {
+    int32_t tile_work;   /* target work per work item; 0 = default          */
+    int32_t block;       /* threads per workgroup; 0 = default               */
+    int32_t grid;        /* persistent workgroups; 0 = one per CU x occupancy */
+    int32_t ydtype;      /* as csrc_plan_opts.ydtype                          */
+} csrc_batch_opts;
+
+/*
+ * csrc_batch_plan_create -- plan for nmat independent products in one
+ * persistent launch.  Per matrix m: n[m], host structure ia[m], ja[m] and
+ * its number of right-hand sides r[m] (1..32).  The plan cuts every matrix
+ * into owner tiles and orders the work list by decreasing cost.
+ */
+int csrc_batch_plan_create(int32_t nmat, const int32_t *n,
+                           const int32_t *const *ia, const int32_t *const *ja,
+                           const int32_t *r, int32_t vdtype,
+                           const csrc_batch_opts *opts, csrc_batch_plan **out);
+int csrc_batch_plan_destroy(csrc_batch_plan *plan);
+int64_t csrc_batch_workspace_bytes(const csrc_batch_plan *plan);
+
+/*
+ * csrc_batch_bind -- upload the plan tables and the per-matrix device
+ * pointers (matrices A[0..nmat), blocks X[m], Y[m] with leading dimensions
+ * ldx[m], ldy[m]) into the workspace.  Host arrays of nmat entries.
+ */
+int csrc_batch_bind(const csrc_batch_plan *plan, const csrc_matrix *A,
+                    const void *const *X, const int64_t *ldx,
+                    void *const *Y, const int64_t *ldy,
+                    void *workspace, int64_t ws_bytes, void *stream);
+
+/*
+ * csrc_batch_run -- one persistent launch computing Y[m] <- A[m] X[m]
+ * (transpose != 0: A[m]^T X[m]) for every bound matrix.  Launches kernels
+ * only (no copies or memsets), so it may be captured into a HIP graph.
+ */
+int csrc_batch_run(const csrc_batch_plan *plan, int32_t transpose,
+                   void *workspace, int64_t ws_bytes, void *stream);
+
+/* Bind then run: the batched forms named after the single products. */
+int csrc_spmv_batched(const csrc_batch_plan *plan, const csrc_matrix *A,
+                      const void *const *X, const int64_t *ldx,
+                      void *const *Y, const int64_t *ldy,
+                      void *workspace, int64_t ws_bytes, void *stream);
+int csrc_spmv_t_batched(const csrc_batch_plan *plan, const csrc_matrix *A,
+                        const void *const *X, const int64_t *ldx,
+                        void *const *Y, const int64_t *ldy,
+                        void *workspace, int64_t ws_bytes, void *stream);
+
+typedef struct csrc_graph csrc_graph;   /* opaque: an instantiated HIP graph */
+
+/*
+ * csrc_batch_graph_create -- build (not capture) a HIP graph whose single
+ * kernel node is the batch launch of csrc_batch_run with these arguments;
+ * csrc_graph_launch replays it on a stream.  The workspace must stay bound.
+ */
+int csrc_batch_graph_create(const csrc_batch_plan *plan, int32_t transpose,
+                            void *workspace, int64_t ws_bytes,
+                            csrc_graph **out);
+int csrc_graph_launch(csrc_graph *graph, void *stream);
+int csrc_graph_destroy(csrc_graph *graph);
+
+/* ------------------------------------------------------------ colouring */
+
+/*
+ * csrc_color -- greedy first-fit colouring of the rows (Sec. 3.2), rows in
+ * ascending index, each taking the smallest colour not held by an earlier
+ * conflicting row.  Host memory.  color[n] receives the classes, *ncolors
+ * their count.  criterion: CSRC_COLOR_WRITE_SET or CSRC_COLOR_DISTANCE2.
+ */
+int csrc_color(int32_t n, const int32_t *ia, const int32_t *ja,
+               int32_t criterion, int32_t *color, int32_t *ncolors);
+
+/* ------------------------------------------------- selection (learned) */
+
+#define CSRC_NFEATURES 12
+
+/*
+ * csrc_features -- the 12 structural features the selector reads, from the
+ * host structure (host memory):
+ *   0 log2(n+1)            1 log2(nnz+1)         2 mean nnz/row
+ *   3 var of nnz/row       4 max nnz/row / mean  5 bandwidth max|i-j| / n
+ *   6 mean |i-j| / n       7 share of pairs with i-j < 64
+ *   8 log2(1 + max writers of one y entry)       9 colours (write sets)/32
+ *  10 log2(working-set bytes / 256 MiB)          11 3x3-block flag
+ * ncolors < 0 makes the library colour the rows itself.
+ */
+int csrc_features(int32_t n, const int32_t *ia, const int32_t *ja,
+                  int32_t vdtype, int32_t ncolors, float *features);
+
+/*
+ * Selector network (12-H-H-K MLP with ReLU and softmax cross-entropy), all
+ * buffers on the device, FP32, row-major weight matrices W[out][in]:
+ *   params layout: W1[H*12] b1[H] W2[H*H] b2[H] W3[K*H] b3[K]
+ * csrc_mlp_param_count returns the number of floats in that layout.
+ */
+int64_t csrc_mlp_param_count(int32_t hidden, int32_t classes);
+
+/*
+ * csrc_mlp_forward -- logits[B*K] and probabilities probs[B*K] for a batch
+ * of B feature rows feats[B*12] (device).  act may be NULL; otherwise it
+ * receives the hidden activations [B*2H] needed by csrc_mlp_backward.
+ */
+int csrc_mlp_forward(int32_t hidden, int32_t classes, int32_t batch,
+                     const float *params, const float *feats, float *act,
+                     float *logits, float *probs, void *stream);
+
+/*
+ * csrc_mlp_backward -- mean softmax cross-entropy loss over the batch for
+ * integer labels[B] (device) and its gradient grads[param_count] (device,
+ * overwritten).  loss (device, 1 float) may be NULL.  Needs the act and
+ * probs written by csrc_mlp_forward on the same batch.
+ */
+int csrc_mlp_backward(int32_t hidden, int32_t classes, int32_t batch,
+                      const float *params, const float *feats,
+                      const float *act, const float *probs,
+                      const int32_t *labels, float *grads, float *loss,
+                      void *stream);
+
+/*
+ * csrc_mlp_adam -- one Adam step (Kingma and Ba) on params with moment
+ * buffers m, v (device, param_count floats each); step is 1-based.
+ */
+int csrc_mlp_adam(int64_t count, float *params, const float *grads, float *m,
+                  float *v, int32_t step, float lr, float beta1, float beta2,
+                  float eps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSRC_H */

@@ -1,0 +1,219 @@
+"""Python face of libcsrc: the C entry points under the same names, plus
+small owners (Matrix, Plan) that keep device buffers alive.
+
+Nothing here computes: each function converts arguments and calls the
+library.  Device memory comes from torch (ROCm) and streams are torch's.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import binding as B
+from .binding import check, np_ptr, t_ptr, stream_ptr
+
+_DT_NP = {B.F64: np.float64, B.F32_: np.float32, B.BF16: np.uint16}
+
+
+def _dt(d):
+    if isinstance(d, str):
+        return B.DTYPES[d]
+    return int(d)
+
+
+def _variant(v):
+    if isinstance(v, str):
+        return B.VARIANTS[v]
+    return int(v)
+
+
+# ----------------------------------------------------------------- host side
+
+def csrc_count(n, rowptr, col, pad=False):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    k = ctypes.c_int64(0)
+    check(B.lib.csrc_count(int(n), np_ptr(rowptr), np_ptr(col), B.PAD_PATTERN if pad else 0,
+                           ctypes.byref(k)), "csrc_count")
+    return k.value
+
+
+def csrc_from_csr(n, rowptr, col, val, pad=False):
+    """CSR -> CSRC on the host (library code).  Returns dict of numpy arrays."""
+    n = int(n)
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    k = csrc_count(n, rowptr, col, pad)
+    ia = np.zeros(n + 1, np.int32)
+    ja = np.zeros(k, np.int32)
+    ad = np.zeros(n, np.float64)
+    al = np.zeros(k, np.float64)
+    au = np.zeros(k, np.float64)
+    check(B.lib.csrc_from_csr(n, np_ptr(rowptr), np_ptr(col), np_ptr(val),
+                              B.PAD_PATTERN if pad else 0, np_ptr(ia), np_ptr(ja), np_ptr(ad),
+                              np_ptr(al), np_ptr(au)), "csrc_from_csr")
+    return {"n": n, "k": k, "ia": ia, "ja": ja, "ad": ad, "al": al, "au": au}
+
+
+def csrc_quantize(a, dtype):
+    d = _dt(dtype)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.empty(a.shape, dtype=_DT_NP[d])
+    check(B.lib.csrc_quantize(a.size, np_ptr(a), d, np_ptr(out)), "csrc_quantize")
+    return out
+
+
+def csrc_color(ia, ja, criterion=B.COLOR_WRITE_SET):
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ja = np.ascontiguousarray(ja, dtype=np.int32)
+    n = ia.shape[0] - 1
+    col = np.zeros(n, np.int32)
+    nc = ctypes.c_int32(0)
+    check(B.lib.csrc_color(n, np_ptr(ia), np_ptr(ja), int(criterion), np_ptr(col),
+                           ctypes.byref(nc)), "csrc_color")
+    return col, nc.value
+
+
+def csrc_features(ia, ja, vdtype="f64", ncolors=-1):
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ja = np.ascontiguousarray(ja, dtype=np.int32)
+    f = np.zeros(B.NFEATURES, np.float32)
+    check(B.lib.csrc_features(ia.shape[0] - 1, np_ptr(ia), np_ptr(ja), _dt(vdtype), int(ncolors),
+                              np_ptr(f)), "csrc_features")
+    return f
+
+
+# --------------------------------------------------------------- device side
+
+class Matrix:
+    """A CSRC matrix in device memory (torch tensors) with its descriptor.
+
+    ``host`` is the dict of csrc_from_csr; values are stored as ``dtype``
+    ("f64", "f32" or "bf16"; rounded by csrc_quantize).  The host structure
+    (ia, ja) is kept for plan creation.
+    """
+
+    def __init__(self, host, dtype="f64", device="cuda"):
+        import torch
+        self.n = int(host["n"])
+        self.k = int(host["k"])
+        self.vdtype = _dt(dtype)
+        self.host_ia = np.ascontiguousarray(host["ia"], dtype=np.int32)
+        self.host_ja = np.ascontiguousarray(host["ja"], dtype=np.int32)
+        self.device = device
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        self.ia = t(self.host_ia)
+        self.ja = t(self.host_ja)
+        self.ad = t(csrc_quantize(host["ad"], self.vdtype))
+        self.al = t(csrc_quantize(host["al"], self.vdtype))
+        self.au = t(csrc_quantize(host["au"], self.vdtype))
+        self.desc = B.CsrcMatrix(self.n, self.vdtype, self.k, t_ptr(self.ia).value or 0,
+                                 t_ptr(self.ja).value or 0, t_ptr(self.ad).value or 0,
+                                 t_ptr(self.al).value or 0, t_ptr(self.au).value or 0)
+
+    @property
+    def xdtype(self):
+        import torch
+        return torch.float64 if self.vdtype == B.F64 else torch.float32
+
+    def nbytes(self):
+        vb = {B.F64: 8, B.F32_: 4, B.BF16: 2}[self.vdtype]
+        return 4 * (self.n + 1) + self.k * (4 + 2 * vb) + self.n * vb
+
+
+class Plan:
+    """A product plan for one matrix structure with its uploaded workspace."""
+
+    def __init__(self, A, variant="private", tile_work=0, lanes=0, block=0,
+                 color_criterion=B.COLOR_WRITE_SET, ydtype="f32", compensated=False,
+                 max_rhs=1, stream=None):
+        import torch
+        self.variant = _variant(variant)
+        opts = B.PlanOpts()
+        check(B.lib.csrc_plan_opts_default(self.variant, ctypes.byref(opts)), "opts")
+        opts.tile_work = int(tile_work)
+        opts.lanes = int(lanes)
+        opts.block = int(block) if block else opts.block
+        opts.color_criterion = int(color_criterion)
+        opts.ydtype = _dt(ydtype)
+        opts.compensated = 1 if compensated else 0
+        opts.max_rhs = int(max_rhs)
+        h = ctypes.c_void_p(0)
+        check(B.lib.csrc_plan_create(A.n, np_ptr(A.host_ia), np_ptr(A.host_ja), A.vdtype,
+                                     ctypes.byref(opts), ctypes.byref(h)), "csrc_plan_create")
+        self._h = h
+        self.n, self.vdtype = A.n, A.vdtype
+        self.ydtype = B.F64 if A.vdtype == B.F64 else _dt(ydtype)
+        self.ws_bytes = int(B.lib.csrc_plan_workspace_bytes(h))
+        self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=A.device)
+        if self.ws_bytes:
+            check(B.lib.csrc_plan_upload(h, t_ptr(self.workspace), self.ws_bytes,
+                                         stream_ptr(stream)), "csrc_plan_upload")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            B.lib.csrc_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = B.PlanInfo()
+        check(B.lib.csrc_plan_get_info(self._h, ctypes.byref(i)), "info")
+        return {f: getattr(i, f) for f, _ in B.PlanInfo._fields_}
+
+    def export(self, what):
+        need = ctypes.c_int64(0)
+        check(B.lib.csrc_plan_export(self._h, int(what), None, 0, ctypes.byref(need)), "export")
+        out = np.zeros(need.value, np.int32)
+        check(B.lib.csrc_plan_export(self._h, int(what), np_ptr(out), need.value,
+                                     ctypes.byref(need)), "export")
+        return out
+
+    @property
+    def ytorch(self):
+        import torch
+        return torch.float64 if self.ydtype == B.F64 else torch.float32
+
+
+def csrc_spmv(A, plan, x, y, stream=None):
+    """y <- A x (overwrites y).  Asynchronous on the stream."""
+    check(B.lib.csrc_spmv(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y),
+                          t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv")
+    return y
+
+
+def csrc_spmv_t(A, plan, x, y, stream=None):
+    """y <- A^T x (overwrites y).  Asynchronous on the stream."""
+    check(B.lib.csrc_spmv_t(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y),
+                            t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_t")
+    return y
+
+
+def csrc_spmm(A, plan, X, Y, stream=None):
+    """Y <- A X for row-major n x r blocks (torch 2-D tensors, row stride = ld)."""
+    r = X.shape[1]
+    check(B.lib.csrc_spmm(ctypes.byref(A.desc), plan.handle, r, t_ptr(X), X.stride(0), t_ptr(Y),
+                          Y.stride(0), t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)),
+          "csrc_spmm")
+    return Y
+
+
+def csrc_spmm_t(A, plan, X, Y, stream=None):
+    r = X.shape[1]
+    check(B.lib.csrc_spmm_t(ctypes.byref(A.desc), plan.handle, r, t_ptr(X), X.stride(0), t_ptr(Y),
+                            Y.stride(0), t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)),
+          "csrc_spmm_t")
+    return Y
+
+
+def spmv(A, plan, x, y=None, transpose=False, stream=None):
+    """Allocating convenience form of csrc_spmv / csrc_spmv_t."""
+    import torch
+    if y is None:
+        y = torch.empty(A.n, dtype=plan.ytorch, device=x.device)
+    return (csrc_spmv_t if transpose else csrc_spmv)(A, plan, x, y, stream)

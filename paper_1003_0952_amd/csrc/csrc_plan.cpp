@@ -1,0 +1,331 @@
+// Host-side setup of a single-matrix product: nnz-guided tiles (Sec. 3.1),
+// effective-range windows and merge lists for the local-buffer variant, pull
+// lists for the owner-computes variant, colour classes (Sec. 3.2), and the
+// layout of the tables in the caller's device workspace.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+int pow2_ceil(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Lanes per row segment: smallest power of two covering the mean number of
+// stored lower entries per row, within [2, 64].
+int auto_lanes(int32_t n, int64_t k)
+{
+    if (n == 0) return 2;
+    double mean = (double)k / n;
+    int g = pow2_ceil((int)std::max(1.0, mean + 0.999));
+    return std::min(64, std::max(2, g));
+}
+
+// Boundaries of `parts` contiguous row blocks of near-equal work, where row
+// i weighs w_i = 2 (ia[i+1]-ia[i]) + 1: block b ends at the first row whose
+// prefix work reaches (b+1)/parts of the total.
+void nnz_partition(int32_t n, const int32_t *ia, int32_t parts, std::vector<int32_t> &s)
+{
+    s.assign(parts + 1, 0);
+    int64_t total = 2 * (int64_t)ia[n] + n;
+    int64_t prefix = 0;   // work of rows [0, i)
+    int32_t b = 1;
+    for (int32_t i = 0; i <= n && b < parts; ++i) {
+        while (b < parts && prefix * parts >= (int64_t)b * total) s[b++] = i;
+        if (i < n) prefix += 2 * (int64_t)(ia[i + 1] - ia[i]) + 1;
+    }
+    while (b < parts) s[b++] = n;
+    s[parts] = n;
+}
+
+// Sorted distinct rows -> intervals, merging gaps of at most `gap` rows.
+void make_intervals(const std::vector<int32_t> &rows, int32_t gap,
+                    std::vector<std::pair<int32_t, int32_t>> &iv)
+{
+    iv.clear();
+    for (int32_t r : rows) {
+        if (!iv.empty() && r - (iv.back().first + iv.back().second) <= gap)
+            iv.back().second = r - iv.back().first + 1;
+        else
+            iv.push_back({r, 1});
+    }
+}
+
+template <class T>
+void put(std::vector<char> &blob, csrc::Table &t, const std::vector<T> &v)
+{
+    t.offset = (int64_t)blob.size();
+    t.bytes = (int64_t)(v.size() * sizeof(T));
+    blob.resize(csrc::align256(t.offset + std::max<int64_t>(t.bytes, 1)));
+    if (t.bytes) std::memcpy(blob.data() + t.offset, v.data(), (size_t)t.bytes);
+}
+
+}  // namespace
+
+extern "C" int csrc_plan_opts_default(int32_t variant, csrc_plan_opts *o)
+{
+    if (!o || variant < 0 || variant >= CSRC_V_COUNT) return CSRC_ERR_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->variant = variant;
+    o->tile_work = 0;
+    o->lanes = 0;
+    o->block = 256;
+    o->color_criterion = CSRC_COLOR_WRITE_SET;
+    o->ydtype = CSRC_F32;
+    o->compensated = 0;
+    o->max_rhs = 1;
+    return CSRC_OK;
+}
+
+static int default_tile_work(int32_t variant)
+{
+    switch (variant) {
+    case CSRC_V_ATOMIC: return 4096;
+    case CSRC_V_PRIVATE: return 8192;
+    case CSRC_V_OWNER: return 16384;
+    default: return 4096;
+    }
+}
+
+extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
+                                const csrc_plan_opts *opts, csrc_plan **out)
+{
+    if (!out || !opts || n < 0 || (n > 0 && (!ia || !ja))) return CSRC_ERR_ARG;
+    if (vdtype < CSRC_F64 || vdtype > CSRC_BF16) return CSRC_ERR_ARG;
+    const csrc_plan_opts &o = *opts;
+    if (o.variant < 0 || o.variant >= CSRC_V_COUNT) return CSRC_ERR_ARG;
+    if (o.block != 0 && (o.block < 64 || o.block > 512 || o.block % 64)) return CSRC_ERR_ARG;
+    if (o.lanes != 0 && (o.lanes < 1 || o.lanes > 64 || (o.lanes & (o.lanes - 1)))) return CSRC_ERR_ARG;
+    if (o.tile_work < 0 || o.max_rhs < 0 || o.max_rhs > csrc::kMaxRhs) return CSRC_ERR_ARG;
+    if (vdtype != CSRC_F64 && o.ydtype != CSRC_F32 && o.ydtype != CSRC_F64) return CSRC_ERR_ARG;
+    *out = nullptr;
+    csrc_plan *p = nullptr;
+    try {
+        p = new csrc_plan();
+        p->n = n;
+        p->k = n ? ia[n] : 0;
+        p->vdtype = vdtype;
+        p->o = o;
+        if (p->o.block == 0) p->o.block = 256;
+        if (p->o.lanes == 0) p->o.lanes = auto_lanes(n, p->k);
+        if (p->o.lanes == 1) p->o.lanes = 2;
+        if (p->o.tile_work == 0) p->o.tile_work = default_tile_work(o.variant);
+        if (p->o.max_rhs == 0) p->o.max_rhs = 1;
+        if (vdtype == CSRC_F64) p->o.ydtype = CSRC_F64;
+        const int acc = csrc::acc_bytes(vdtype);
+        const int v = p->o.variant;
+        std::vector<char> &blob = p->blob;
+
+        if (v != CSRC_V_PLAIN && v != CSRC_V_COLOR && n > 0) {
+            int64_t total = 2 * p->k + n;
+            int64_t parts = std::max<int64_t>(1, (total + p->o.tile_work - 1) / p->o.tile_work);
+            if (parts > (int64_t)1 << 30) { delete p; return CSRC_ERR_TOO_LARGE; }
+            nnz_partition(n, ia, (int32_t)parts, p->tiles);
+            p->ntiles = (int32_t)parts;
+            for (int32_t t = 0; t < p->ntiles; ++t)
+                p->max_tile_rows = std::max(p->max_tile_rows, p->tiles[t + 1] - p->tiles[t]);
+        }
+
+        if (v == CSRC_V_PRIVATE && n > 0) {
+            // Effective range of a tile (Sec. 3.1): its own rows plus the
+            // rows below it that its loops write.  The latter are stored as a
+            // few intervals (windows) whose slots hold the tile's partials.
+            std::vector<int32_t> stamp(n, -1), tg;
+            std::vector<std::pair<int32_t, int32_t>> iv;
+            p->iv_ptr.assign(p->ntiles + 1, 0);
+            int64_t slots = 0;
+            for (int32_t t = 0; t < p->ntiles; ++t) {
+                int32_t r0 = p->tiles[t], r1 = p->tiles[t + 1];
+                tg.clear();
+                for (int32_t q = ia[r0]; q < ia[r1]; ++q) {
+                    int32_t j = ja[q];
+                    if (j < r0 && stamp[j] != t) { stamp[j] = t; tg.push_back(j); }
+                }
+                std::sort(tg.begin(), tg.end());
+                int32_t gap = 16;
+                make_intervals(tg, gap, iv);
+                while ((int)iv.size() > csrc::kMaxIntervals) {
+                    gap *= 2;
+                    make_intervals(tg, gap, iv);
+                }
+                int32_t w = 0;
+                for (auto &e : iv) {
+                    p->iv_row.push_back(e.first);
+                    p->iv_len.push_back(e.second);
+                    p->iv_slot.push_back(w);
+                    p->iv_goff.push_back(slots + w);
+                    w += e.second;
+                }
+                slots += w;
+                p->iv_ptr[t + 1] = (int32_t)p->iv_row.size();
+                p->max_window = std::max(p->max_window, w);
+                p->max_intervals = std::max(p->max_intervals, (int32_t)iv.size());
+            }
+            p->window_slots = slots;
+            // merge lists: intervals touching each block of kMergeBlock rows,
+            // in ascending interval (= tile) order
+            int32_t nb = (n + csrc::kMergeBlock - 1) / csrc::kMergeBlock;
+            p->nmerge_blocks = nb;
+            p->mb_ptr.assign(nb + 1, 0);
+            int32_t ni = (int32_t)p->iv_row.size();
+            for (int32_t g = 0; g < ni; ++g) {
+                int32_t b0 = p->iv_row[g] / csrc::kMergeBlock;
+                int32_t b1 = (p->iv_row[g] + p->iv_len[g] - 1) / csrc::kMergeBlock;
+                for (int32_t b = b0; b <= b1; ++b) p->mb_ptr[b + 1]++;
+            }
+            for (int32_t b = 0; b < nb; ++b) p->mb_ptr[b + 1] += p->mb_ptr[b];
+            p->mb_iv.resize(p->mb_ptr[nb]);
+            std::vector<int32_t> fill(p->mb_ptr.begin(), p->mb_ptr.end() - 1);
+            for (int32_t g = 0; g < ni; ++g) {
+                int32_t b0 = p->iv_row[g] / csrc::kMergeBlock;
+                int32_t b1 = (p->iv_row[g] + p->iv_len[g] - 1) / csrc::kMergeBlock;
+                for (int32_t b = b0; b <= b1; ++b) p->mb_iv[fill[b]++] = g;
+            }
+            p->lds_bytes = (int64_t)(p->max_tile_rows + 1) * 4 + (int64_t)p->max_tile_rows * 2 * acc +
+                           (int64_t)p->max_window * 2 * acc + (int64_t)(p->max_intervals + 1) * 8 + 64;
+            if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
+        }
+
+        if (v == CSRC_V_OWNER && n > 0) {
+            // Rows of later tiles that scatter into tile t, as intervals.
+            std::vector<int32_t> tile_of(n);
+            for (int32_t t = 0; t < p->ntiles; ++t)
+                for (int32_t r = p->tiles[t]; r < p->tiles[t + 1]; ++r) tile_of[r] = t;
+            std::vector<std::vector<int32_t>> pull(p->ntiles);
+            for (int32_t i = 0; i < n; ++i) {
+                int32_t ti = tile_of[i];
+                int32_t last = -1;
+                for (int32_t q = ia[i]; q < ia[i + 1]; ++q) {
+                    int32_t tj = tile_of[ja[q]];
+                    if (tj != ti && tj != last) {       // ja ascending -> tj ascending
+                        pull[tj].push_back(i);
+                        last = tj;
+                    }
+                }
+            }
+            std::vector<std::pair<int32_t, int32_t>> iv;
+            p->iv_ptr.assign(p->ntiles + 1, 0);
+            for (int32_t t = 0; t < p->ntiles; ++t) {
+                make_intervals(pull[t], 4, iv);
+                int32_t w = 0;
+                for (auto &e : iv) {
+                    p->iv_row.push_back(e.first);
+                    p->iv_len.push_back(e.second);
+                    w += e.second;
+                }
+                p->pulled_rows += w;
+                p->iv_ptr[t + 1] = (int32_t)p->iv_row.size();
+                p->max_window = std::max(p->max_window, w);
+                p->max_intervals = std::max(p->max_intervals, (int32_t)iv.size());
+                std::vector<int32_t>().swap(pull[t]);
+            }
+            p->lds_bytes = (int64_t)(p->max_tile_rows + 1) * 4 + (int64_t)p->max_tile_rows * 2 * acc + 64;
+            if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
+        }
+
+        if (v == CSRC_V_COLOR && n > 0) {
+            p->color.resize(n);
+            int st = csrc::color_rows(n, ia, ja, p->o.color_criterion, p->color.data(), &p->ncolors);
+            if (st) { delete p; return st; }
+            p->cptr.assign(p->ncolors + 1, 0);
+            for (int32_t i = 0; i < n; ++i) p->cptr[p->color[i] + 1]++;
+            for (int32_t c = 0; c < p->ncolors; ++c) p->cptr[c + 1] += p->cptr[c];
+            p->crow.resize(n);
+            std::vector<int32_t> fill(p->cptr.begin(), p->cptr.end() - 1);
+            for (int32_t i = 0; i < n; ++i) p->crow[fill[p->color[i]]++] = i;
+        }
+
+        // workspace image
+        put(blob, p->t_tiles, p->tiles);
+        put(blob, p->t_iv_ptr, p->iv_ptr);
+        put(blob, p->t_iv_row, p->iv_row);
+        put(blob, p->t_iv_len, p->iv_len);
+        put(blob, p->t_iv_slot, p->iv_slot);
+        put(blob, p->t_iv_goff, p->iv_goff);
+        put(blob, p->t_mb_ptr, p->mb_ptr);
+        put(blob, p->t_mb_iv, p->mb_iv);
+        put(blob, p->t_crow, p->crow);
+        p->blob_bytes = (int64_t)blob.size();
+        p->t_partials.offset = p->blob_bytes;
+        p->t_partials.bytes = p->window_slots * acc * p->o.max_rhs;
+        p->ws_bytes = csrc::align256(p->blob_bytes + p->t_partials.bytes);
+        if (v == CSRC_V_PLAIN) p->ws_bytes = 0;
+        *out = p;
+        return CSRC_OK;
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return CSRC_ERR_NOMEM;
+    }
+}
+
+extern "C" int csrc_plan_destroy(csrc_plan *p)
+{
+    delete p;
+    return CSRC_OK;
+}
+
+extern "C" int64_t csrc_plan_workspace_bytes(const csrc_plan *p) { return p ? p->ws_bytes : -1; }
+
+extern "C" int csrc_plan_upload(const csrc_plan *p, void *ws, int64_t bytes, void *stream)
+{
+    if (!p) return CSRC_ERR_ARG;
+    if (p->ws_bytes == 0) return CSRC_OK;
+    if (!ws || bytes < p->ws_bytes) return CSRC_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(ws, p->blob.data(), (size_t)p->blob_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return CSRC_ERR_HIP;
+    // the host image stays owned by the plan; wait so callers may reuse it freely
+    if (hipStreamSynchronize(s) != hipSuccess) return CSRC_ERR_HIP;
+    return CSRC_OK;
+}
+
+extern "C" int csrc_plan_get_info(const csrc_plan *p, csrc_plan_info *info)
+{
+    if (!p || !info) return CSRC_ERR_ARG;
+    info->variant = p->o.variant;
+    info->ntiles = p->ntiles;
+    info->ncolors = p->ncolors;
+    info->lanes = p->o.lanes;
+    info->block = p->o.block;
+    info->max_tile_rows = p->max_tile_rows;
+    info->max_window = p->max_window;
+    info->nintervals = (int32_t)p->iv_row.size();
+    info->window_slots = p->window_slots;
+    info->pulled_rows = p->pulled_rows;
+    info->lds_bytes = p->lds_bytes;
+    info->workspace_bytes = p->ws_bytes;
+    return CSRC_OK;
+}
+
+extern "C" int csrc_plan_export(const csrc_plan *p, int32_t what, int32_t *dst, int64_t count,
+                                int64_t *needed)
+{
+    if (!p || !needed) return CSRC_ERR_ARG;
+    std::vector<int32_t> v;
+    if (what == 0) {
+        v = p->tiles;
+    } else if (what == 1) {
+        v = p->color;
+    } else if (what == 2) {
+        for (int32_t t = 0; t < (int32_t)p->iv_ptr.size() - 1; ++t)
+            for (int32_t g = p->iv_ptr[t]; g < p->iv_ptr[t + 1]; ++g) {
+                v.push_back(t);
+                v.push_back(p->iv_row[g]);
+                v.push_back(p->iv_len[g]);
+            }
+    } else {
+        return CSRC_ERR_ARG;
+    }
+    *needed = (int64_t)v.size();
+    if (count < (int64_t)v.size()) return dst ? CSRC_ERR_ARG : CSRC_OK;
+    if (!v.empty()) std::memcpy(dst, v.data(), v.size() * 4);
+    return CSRC_OK;
+}

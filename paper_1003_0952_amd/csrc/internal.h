@@ -1,0 +1,78 @@
+// Internal declarations shared by the host and device sources of libcsrc.
+#pragma once
+
+#include <cstdint>
+#include <cstddef>
+#include <vector>
+#include <new>
+
+#include "../../include/csrc.h"
+
+namespace csrc {
+
+constexpr int kMaxRhs = 32;
+constexpr int kMergeBlock = 256;      // rows per merge workgroup (PRIVATE)
+constexpr int kMaxIntervals = 64;     // window intervals per PRIVATE tile
+constexpr int64_t kLdsBudget = 160 * 1024;   // bytes of LDS per CU on gfx950
+
+inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+inline int value_bytes(int32_t dt) { return dt == CSRC_F64 ? 8 : (dt == CSRC_F32 ? 4 : 2); }
+inline int acc_bytes(int32_t vdt) { return vdt == CSRC_F64 ? 8 : 4; }
+
+// A table placed in the device workspace.
+struct Table {
+    int64_t offset = 0;   // bytes from the workspace base
+    int64_t bytes = 0;
+};
+
+// Device-side view of a single-matrix plan (all pointers into the workspace).
+struct PlanDev {
+    const int32_t *tiles;      // ntiles+1 row boundaries
+    const int32_t *iv_ptr;     // ntiles+1: intervals of each tile
+    const int32_t *iv_row;     // first row of each interval
+    const int32_t *iv_len;     // rows in each interval
+    const int32_t *iv_slot;    // slot of the interval's first row in its tile window
+    const int64_t *iv_goff;    // global partial offset of the interval's first row
+    const int32_t *mb_ptr;     // merge blocks: intervals touching each block
+    const int32_t *mb_iv;
+    const int32_t *crow;       // rows sorted by colour
+    const int32_t *cptr;       // colour class boundaries (host copy used for launches)
+    void *partials;            // partial buffer (PRIVATE)
+};
+
+struct csrc_plan_impl;
+
+}  // namespace csrc
+
+struct csrc_plan {
+    int32_t n = 0;
+    int64_t k = 0;
+    int32_t vdtype = CSRC_F64;
+    csrc_plan_opts o{};
+    int32_t ntiles = 0;
+    int32_t max_tile_rows = 0;
+    int32_t max_window = 0;     // PRIVATE: slots; OWNER: pulled rows
+    int32_t max_intervals = 0;
+    int64_t window_slots = 0;
+    int64_t pulled_rows = 0;
+    int64_t lds_bytes = 0;
+    int32_t ncolors = 0;
+    int32_t nmerge_blocks = 0;
+    // host tables
+    std::vector<int32_t> tiles, iv_ptr, iv_row, iv_len, iv_slot, mb_ptr, mb_iv;
+    std::vector<int64_t> iv_goff;
+    std::vector<int32_t> color, crow, cptr;
+    // layout of the workspace
+    csrc::Table t_tiles, t_iv_ptr, t_iv_row, t_iv_len, t_iv_slot, t_iv_goff,
+        t_mb_ptr, t_mb_iv, t_crow, t_partials;
+    int64_t blob_bytes = 0;      // bytes of uploaded tables (prefix of workspace)
+    int64_t ws_bytes = 0;
+    std::vector<char> blob;      // host image of the uploaded tables
+};
+
+namespace csrc {
+// host helpers implemented in csrc_host.cpp
+int color_rows(int32_t n, const int32_t *ia, const int32_t *ja, int32_t criterion,
+               int32_t *color, int32_t *ncolors);
+}

@@ -1,0 +1,131 @@
+"""GPU parity of y = A x and y = A^T x, every variant, FP64, through the C ABI.
+
+Bar: relative infinity-norm error <= 1e-12 against the FP64 oracle;
+integer-valued inputs bit-exact for every variant (all partial sums are
+integers below 2^24, so every summation order is exact).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import reference as R
+from tests.helpers import small_cases, oracle_csrc, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["plain", "atomic", "private", "color", "owner"]
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def run(torch, C, host, x, variant, transpose, dtype="f64", **kw):
+    A = C.Matrix(host, dtype)
+    plan = C.Plan(A, variant, **kw)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", A.xdtype)
+    y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+    (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64), plan
+
+
+CASES = small_cases()
+INT_CASES = small_cases("int")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_fp64_parity(torch_cuda, variant, case):
+    import paper_1003_0952_amd as C
+    name, a, x = CASES[case]
+    print(f"case {name} variant {variant}", flush=True)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    for transpose in (False, True):
+        y, _ = run(torch_cuda, C, host, x, variant, transpose)
+        ref = (R.spmv_t if transpose else R.spmv)(c, x)
+        assert rel_inf(y, ref) <= TOL, (name, variant, transpose, rel_inf(y, ref))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("case", range(len(INT_CASES)), ids=[c[0] for c in INT_CASES])
+def test_integer_bit_exact(torch_cuda, variant, case):
+    import paper_1003_0952_amd as C
+    name, a, x = INT_CASES[case]
+    print(f"case {name} variant {variant} (integer)", flush=True)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    for transpose in (False, True):
+        y, _ = run(torch_cuda, C, host, x, variant, transpose)
+        ref = (R.spmv_t if transpose else R.spmv)(c, x)
+        assert np.array_equal(y, ref), (name, variant, transpose)
+
+
+@pytest.mark.parametrize("variant", ["atomic", "private", "owner", "color"])
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16, 32, 64])
+def test_lane_widths(torch_cuda, variant, lanes):
+    import paper_1003_0952_amd as C
+    name, a, x = CASES[1]
+    print(f"case {name} variant {variant} lanes {lanes}", flush=True)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    for block in (64, 256, 512):
+        y, _ = run(torch_cuda, C, host, x, variant, False, lanes=lanes, block=block, tile_work=1500)
+        assert rel_inf(y, R.spmv(c, x)) <= TOL
+
+
+def test_error_paths(torch_cuda):
+    import paper_1003_0952_amd as C
+    torch = torch_cuda
+    name, a, x = CASES[0]
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    A = C.Matrix(host, "f64")
+    plan = C.Plan(A, "private")
+    xt = torch.from_numpy(x).cuda()
+    with pytest.raises(C.CsrcError) as e:
+        C.csrc_spmv(A, plan, xt, xt)
+    assert e.value.status == -6
+    other = C.Matrix(C.csrc_from_csr(*(lambda b: (b.n, b.rowptr, b.col, b.val))(CASES[2][1])), "f64")
+    with pytest.raises(C.CsrcError) as e:
+        C.csrc_spmv(other, plan, torch.zeros(other.n, dtype=torch.float64, device="cuda"),
+                    torch.zeros(other.n, dtype=torch.float64, device="cuda"))
+    assert e.value.status == -10
+    import ctypes
+    from paper_1003_0952_amd import binding as B
+    y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    st = B.lib.csrc_spmv(ctypes.byref(A.desc), plan.handle, B.t_ptr(xt), B.t_ptr(y),
+                         B.t_ptr(plan.workspace), 16, B.stream_ptr())
+    assert st == -7
+
+
+def test_empty_matrix(torch_cuda):
+    import paper_1003_0952_amd as C
+    host = C.csrc_from_csr(0, [0], [], [])
+    A = C.Matrix(host, "f64")
+    for v in VARIANTS:
+        plan = C.Plan(A, v)
+        e = torch_cuda.zeros(0, dtype=torch_cuda.float64, device="cuda")
+        C.csrc_spmv(A, plan, e, e)
+
+
+def test_repeated_products_identical(torch_cuda):
+    """Plans are immutable: products repeat (deterministic variants bit-identically)."""
+    import paper_1003_0952_amd as C
+    torch = torch_cuda
+    name, a, x = CASES[1]
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    A = C.Matrix(host, "f64")
+    xt = torch.from_numpy(x).cuda()
+    for v in VARIANTS:
+        plan = C.Plan(A, v)
+        y1 = C.spmv(A, plan, xt).clone()
+        y2 = C.spmv(A, plan, xt)
+        torch.cuda.synchronize()
+        assert rel_inf(y1.cpu().numpy(), y2.cpu().numpy()) <= 1e-15

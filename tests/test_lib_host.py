@@ -1,0 +1,218 @@
+"""Host-side library logic against the oracle (no GPU needed).
+
+csrc_from_csr, csrc_quantize, csrc_color and the plan's tiles must agree with
+the oracle bit for bit; plan windows and pull lists must cover every scatter
+exactly once.  Also checks that libcsrc exports every symbol csrc.h declares.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import reference as R
+from synth import patterns as P, workloads as W
+from synth.values import fill_values
+
+import paper_1003_0952_amd as C
+from paper_1003_0952_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "csrc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(csrc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 30
+    for name in names:
+        assert hasattr(B.lib, name), name
+    assert B.lib.csrc_version() >= 10000
+
+
+MATS = [
+    lambda: W.quad64()[0],
+    lambda: W.hex_mesh(11)[0],
+    lambda: W.hex_mesh(11, "random")[0],
+    lambda: W.hex_mesh(11, "rcm")[0],
+    lambda: W.tet_mesh(5)[0],
+    lambda: fill_values(P.banded(2500, 40, 0.25, 3), 4),
+    lambda: fill_values(P.reorder(P.power_law(4000, 16.0, 2.5, 7), P.random_order(4000, 8)), 5),
+]
+
+
+@pytest.mark.parametrize("make", MATS)
+def test_from_csr_bit_exact(make):
+    a = make()
+    ref = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+    got = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    assert got["k"] == ref["k"]
+    for key in ("ia", "ja"):
+        assert np.array_equal(got[key], ref[key]), key
+    for key in ("ad", "al", "au"):
+        assert np.array_equal(got[key].view(np.uint64), ref[key].view(np.uint64)), key
+
+
+def test_from_csr_unsorted_and_errors():
+    a = W.hex_mesh(5)[0]
+    rng = np.random.default_rng(1)
+    col, val = a.col.copy(), a.val.copy()
+    for i in range(a.n):
+        s, e = a.rowptr[i], a.rowptr[i + 1]
+        p = rng.permutation(e - s) + s
+        col[s:e], val[s:e] = a.col[p], a.val[p]
+    ref = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+    got = C.csrc_from_csr(a.n, a.rowptr, col, val)
+    for key in ("ia", "ja", "ad", "al", "au"):
+        assert np.array_equal(got[key], ref[key])
+    cases = [
+        ((2, [0, 2, 3], [0, 0, 1], [1.0, 1.0, 1.0]), B.ERR_DUPLICATE),
+        ((2, [0, 1, 2], [0, 2], [1.0, 1.0]), B.ERR_INDEX_RANGE),
+        ((2, [0, 1, 3], [0, 0, 1], [1.0, 1.0, 1.0]), B.ERR_NOT_STRUCT_SYM),
+        ((2, [0, 1, 3], [0, 0, -1], [1.0, 1.0, 1.0]), B.ERR_INDEX_RANGE),
+    ]
+    for args, code in cases:
+        with pytest.raises(C.CsrcError) as e:
+            C.csrc_from_csr(*args)
+        assert e.value.status == code
+    got = C.csrc_from_csr(2, [0, 1, 3], [0, 0, 1], [1.0, 7.0, 2.0], pad=True)
+    ref = R.csr_to_csrc(2, [0, 1, 3], [0, 0, 1], [1.0, 7.0, 2.0], pad=True)
+    for key in ("ia", "ja", "ad", "al", "au"):
+        assert np.array_equal(got[key], ref[key])
+    z = C.csrc_from_csr(0, [0], [], [])
+    assert z["k"] == 0
+
+
+def test_quantize_bit_exact():
+    rng = np.random.default_rng(5)
+    v = np.concatenate([rng.uniform(-3, 3, 10000), [0.0, -0.0, 1 + 2**-8, 1 + 3 * 2**-9, 1e-40, 3e38,
+                                                    np.inf, -np.inf]])
+    assert np.array_equal(C.csrc_quantize(v, "f32").view(np.uint32), R.to_f32(v).view(np.uint32))
+    assert np.array_equal(C.csrc_quantize(v, "bf16"), R.to_bf16_bits(v))
+    assert np.array_equal(C.csrc_quantize(v, "f64"), v)
+
+
+COLOR_MATS = [
+    lambda: W.quad64()[0],
+    lambda: P.q1_hex(16, 16, 16),
+    lambda: P.reorder(P.q1_hex(9, 9, 9), P.random_order(729, 2)),
+    lambda: P.kuhn_tet(6, 6, 6, 3),
+    lambda: P.banded(3000, 20, 0.3, 2),
+    lambda: P.power_law(3000, 12.0, 2.5, 4),
+]
+
+
+@pytest.mark.parametrize("make", COLOR_MATS)
+@pytest.mark.parametrize("criterion", [0, 1])
+def test_colouring_bit_exact(make, criterion):
+    a = make()
+    if a.val is None:
+        fill_values(a, 1)
+    c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+    ref, nref = R.color(c, criterion)
+    got, ngot = C.csrc_color(c["ia"], c["ja"], criterion)
+    assert ngot == nref
+    assert np.array_equal(got, ref)
+
+
+def host_matrix(a):
+    c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+
+    class H:
+        pass
+    h = H()
+    h.n, h.k, h.vdtype = c["n"], c["k"], 0
+    h.host_ia, h.host_ja, h.device = c["ia"], c["ja"], "cpu"
+    return c, h
+
+
+class HostPlan(C.Plan):
+    """Plan built on the host only (no workspace upload)."""
+
+    def __init__(self, h, variant, **kw):
+        import ctypes
+        opts = B.PlanOpts()
+        B.check(B.lib.csrc_plan_opts_default(B.VARIANTS[variant], ctypes.byref(opts)))
+        for k, v in kw.items():
+            setattr(opts, k, v)
+        hh = ctypes.c_void_p(0)
+        B.check(B.lib.csrc_plan_create(h.n, B.np_ptr(h.host_ia), B.np_ptr(h.host_ja), 0,
+                                       ctypes.byref(opts), ctypes.byref(hh)))
+        self._h = hh
+
+
+@pytest.mark.parametrize("make", MATS[:5])
+@pytest.mark.parametrize("work", [512, 4096, 30000])
+def test_plan_tiles_match_partition(make, work):
+    c, h = host_matrix(make())
+    for variant in ("atomic", "private", "owner"):
+        p = HostPlan(h, variant, tile_work=work)
+        assert np.array_equal(p.export(0), R.partition_for_target(c["ia"], work))
+
+
+@pytest.mark.parametrize("make", MATS[:5])
+def test_private_windows_cover_effective_ranges(make):
+    c, h = host_matrix(make())
+    p = HostPlan(h, "private", tile_work=2048)
+    tiles = p.export(0)
+    iv = p.export(2).reshape(-1, 3)
+    for t in range(len(tiles) - 1):
+        r0, r1 = tiles[t], tiles[t + 1]
+        mine = iv[iv[:, 0] == t]
+        need = R.out_of_tile_targets(c, r0, r1)
+        covered = np.concatenate([np.arange(s, s + L) for _, s, L in mine]) if len(mine) else np.zeros(0, int)
+        # intervals are disjoint, ascending, below r0, and contain every target
+        assert np.all(np.diff(covered) > 0)
+        assert covered.size == 0 or covered.max() < r0
+        assert np.all(np.isin(need, covered))
+    info = p.info()
+    assert info["window_slots"] == sum(iv[:, 2])
+
+
+@pytest.mark.parametrize("make", MATS[:5])
+def test_owner_pull_lists_cover_every_scatter(make):
+    c, h = host_matrix(make())
+    p = HostPlan(h, "owner", tile_work=2048)
+    tiles = p.export(0)
+    iv = p.export(2).reshape(-1, 3)
+    tile_of = np.searchsorted(tiles, np.arange(c["n"]), side="right") - 1
+    rows = np.repeat(np.arange(c["n"]), np.diff(c["ia"]))
+    ti, tj = tile_of[rows], tile_of[c["ja"]]
+    cross = ti != tj
+    pulled = set()
+    for t, s, L in iv:
+        for r in range(s, s + L):
+            pulled.add((t, r))
+    for r, t in zip(rows[cross], tj[cross]):
+        assert (t, r) in pulled
+
+
+def test_plan_options_rejected():
+    c, h = host_matrix(W.quad64()[0])
+    with pytest.raises(C.CsrcError):
+        HostPlan(h, "private", lanes=3)
+    with pytest.raises(C.CsrcError):
+        HostPlan(h, "private", block=100)
+
+
+def test_features_definition():
+    a, _ = W.quad64()
+    c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+    f = C.csrc_features(c["ia"], c["ja"], "f64", -1)
+    lens = np.diff(a.rowptr)
+    assert f[0] == pytest.approx(np.log2(a.n + 1))
+    assert f[1] == pytest.approx(np.log2(a.nnz + 1))
+    assert f[2] == pytest.approx(lens.mean(), rel=1e-6)
+    assert f[3] == pytest.approx(lens.var(), rel=1e-5)
+    assert f[5] == pytest.approx(65 / 4096)
+    assert f[9] == pytest.approx(7 / 32)
+    assert f[11] == 0.0
+    t = P.kuhn_tet(4, 4, 4, 3)
+    fill_values(t, 1)
+    ct = R.csr_to_csrc(t.n, t.rowptr, t.col, t.val)
+    assert C.csrc_features(ct["ia"], ct["ja"], "f64", 3)[11] == 1.0
