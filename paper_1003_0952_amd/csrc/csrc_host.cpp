@@ -237,7 +237,7 @@ namespace csrc {
 int color_rows(int32_t n, const int32_t *ia, const int32_t *ja, int32_t criterion,
                int32_t *color, int32_t *ncolors)
 {
-    if (n < 0 || !ncolors || (n > 0 && (!ia || !ja || !color))) return CSRC_ERR_ARG;
+    if (n < 0 || !ncolors || (n > 0 && (!ia || !color || (ia[n] > 0 && !ja)))) return CSRC_ERR_ARG;
     if (criterion != CSRC_COLOR_WRITE_SET && criterion != CSRC_COLOR_DISTANCE2) return CSRC_ERR_ARG;
     try {
         *ncolors = 0;
@@ -313,7 +313,7 @@ extern "C" int csrc_color(int32_t n, const int32_t *ia, const int32_t *ja, int32
 extern "C" int csrc_features(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
                              int32_t ncolors, float *f)
 {
-    if (n < 0 || !f || (n > 0 && (!ia || !ja))) return CSRC_ERR_ARG;
+    if (n < 0 || !f || (n > 0 && (!ia || (ia[n] > 0 && !ja)))) return CSRC_ERR_ARG;
     try {
         for (int q = 0; q < CSRC_NFEATURES; ++q) f[q] = 0.f;
         if (n == 0) return CSRC_OK;

@@ -98,7 +98,7 @@ static int default_tile_work(int32_t variant)
 extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
                                 const csrc_plan_opts *opts, csrc_plan **out)
 {
-    if (!out || !opts || n < 0 || (n > 0 && (!ia || !ja))) return CSRC_ERR_ARG;
+    if (!out || !opts || n < 0 || (n > 0 && (!ia || (ia[n] > 0 && !ja)))) return CSRC_ERR_ARG;
     if (vdtype < CSRC_F64 || vdtype > CSRC_BF16) return CSRC_ERR_ARG;
     const csrc_plan_opts &o = *opts;
     if (o.variant < 0 || o.variant >= CSRC_V_COUNT) return CSRC_ERR_ARG;
