@@ -113,12 +113,11 @@ def time_plan(C, torch, cp, plan, steps, warmup, per_product=False):
 
 
 CANDIDATES = [
-    ("owner", dict(tile_work=16384)),
-    ("owner", dict(tile_work=32768)),
-    ("owner", dict(tile_work=8192)),
-    ("private", dict(tile_work=8192)),
-    ("private", dict(tile_work=16384)),
-    ("atomic", dict(tile_work=4096)),
+    ("private", dict(tile_work=8192, block=512)),
+    ("private", dict(tile_work=4096, block=256)),
+    ("private", dict(tile_work=4096, block=512)),
+    ("owner", dict(tile_work=16384, block=512)),
+    ("atomic", dict(tile_work=8192, block=512)),
     ("color", dict()),
 ]
 

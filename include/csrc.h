@@ -59,6 +59,11 @@ const char *csrc_status_string(int status);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t csrc_version(void);
 
+/* The hipError_t of the last HIP call that failed in this thread inside the
+ * library (0 if none), and its name; they explain a CSRC_ERR_HIP. */
+int32_t csrc_last_hip_error(void);
+const char *csrc_last_hip_error_string(void);
+
 /* ------------------------------------------------------------ data types */
 typedef enum csrc_dtype {
     CSRC_F64 = 0,
@@ -106,7 +111,9 @@ int csrc_quantize(int64_t count, const double *src, int32_t dtype, void *dst);
 
 /* ----------------------------------------------------------- matrices */
 
-/* A CSRC matrix resident on the device.  Value arrays hold vdtype. */
+/* A CSRC matrix resident on the device.  Value arrays hold vdtype.  ja, al
+ * and au must be 16-byte aligned (8-byte for BF16 values), as hipMalloc'd
+ * memory is: the kernels read them with vector loads (CSRC_ERR_ARG if not). */
 typedef struct csrc_matrix {
     int32_t n;
     int32_t vdtype;        /* csrc_dtype of ad, al, au                        */
@@ -129,9 +136,10 @@ typedef enum csrc_variant {
     /* One thread per row; y cleared, then every row sum and every mirrored
        upper product added with a global atomic.  The plain baseline.        */
     CSRC_V_PLAIN = 0,
-    /* Row segments of g lanes (csrc_plan_opts.lanes) stream ja/al/au
-       coalesced, reduce the row sum with lane shuffles and add it, and each
-       scattered au*x_i, with global atomics (Sec. 3: atomic primitives).      */
+    /* Atomic scatter (Sec. 3: atomic primitives): y cleared, tiles stream
+       ja/al/au; scatters below the tile are global atomic adds, scatters
+       inside it and the row sums meet in LDS and are added to y with one
+       global atomic per row.                                                  */
     CSRC_V_ATOMIC = 1,
     /* Local buffers (Sec. 3.1) per workgroup: a tile of nnz-balanced rows
        accumulates its own rows and its out-of-tile targets (its effective
@@ -139,7 +147,9 @@ typedef enum csrc_variant {
        y in ascending tile order.                                              */
     CSRC_V_PRIVATE = 2,
     /* Colourful method (Sec. 3.2): rows grouped into conflict-free colour
-       classes, processed one class per launch with plain stores.            */
+       classes, processed one class per launch with plain stores; rows are
+       walked by segments of g lanes (csrc_plan_opts.lanes) with the row sum
+       reduced by lane shuffles.                                              */
     CSRC_V_COLOR = 3,
     /* Owner-computes: the workgroup that owns a tile of y also visits the
        rows above it that scatter into the tile, so every y entry is formed

@@ -270,11 +270,28 @@ def partition(ia, parts):
     return np.concatenate([[0], s, [n]]).astype(np.int64)
 
 
-def partition_for_target(ia, target):
-    """Partition with ceil(total work / target) blocks."""
+def cap_rows(bounds, max_rows):
+    """Split every block of more than ``max_rows`` rows into m = ceil(rows /
+    max_rows) pieces with boundaries r0 + floor(p * rows / m), p = 0..m.
+
+    (A GPU tile keeps per-row state of its block on chip, so its row count
+    needs a bound; blocks within the bound are unchanged.)
+    """
+    out = [int(bounds[0])]
+    for b in range(len(bounds) - 1):
+        r0, r1 = int(bounds[b]), int(bounds[b + 1])
+        rows = r1 - r0
+        m = max(1, -(-rows // max_rows))
+        for p in range(1, m + 1):
+            out.append(r0 + (p * rows) // m)
+    return np.array(out, dtype=np.int64)
+
+
+def partition_for_target(ia, target, max_rows=2048):
+    """Partition with ceil(total work / target) blocks, then the row cap."""
     total = int(row_weights(ia).sum())
     parts = max(1, -(-total // int(target)))
-    return partition(ia, parts)
+    return cap_rows(partition(ia, parts), max_rows)
 
 
 def out_of_tile_targets(c, r0, r1):

@@ -153,7 +153,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and B is not None and getattr(B, "lib", None) is not None:
             B.lib.csrc_plan_destroy(h)
             self._h = None
 

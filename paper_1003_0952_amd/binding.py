@@ -11,6 +11,12 @@ import os
 
 import numpy as np
 
+# torch must be loaded first: its HIP runtime (soname libamdhip64.so.7) then
+# satisfies libcsrc's dependency, so the process holds one HIP runtime and the
+# library sees torch's devices, memory and streams.  Loading libcsrc first
+# would pull a second runtime copy in beside torch's.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libcsrc.so")
 
@@ -57,6 +63,8 @@ class CsrcError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
         msg = _lib.csrc_status_string(status).decode()
+        if status == ERR_HIP:
+            msg += f" [{_lib.csrc_last_hip_error_string().decode()}]"
         super().__init__(f"{where}: {msg} ({status})" if where else f"{msg} ({status})")
 
 
@@ -97,6 +105,8 @@ def _sig(name, res, args):
 
 _sig("csrc_status_string", ctypes.c_char_p, [ctypes.c_int])
 _sig("csrc_version", I32, [])
+_sig("csrc_last_hip_error", I32, [])
+_sig("csrc_last_hip_error_string", ctypes.c_char_p, [])
 _sig("csrc_count", ctypes.c_int, [I32, P, P, I32, P])
 _sig("csrc_from_csr", ctypes.c_int, [I32, P, P, P, I32, P, P, P, P, P])
 _sig("csrc_quantize", ctypes.c_int, [I64, P, I32, P])

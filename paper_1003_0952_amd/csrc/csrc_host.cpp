@@ -6,7 +6,25 @@
 #include <numeric>
 #include <vector>
 
+#include <hip/hip_runtime_api.h>
+
 #include "internal.h"
+
+namespace csrc {
+static thread_local int g_last_hip = 0;
+int hip_status(int e)
+{
+    if (e == 0) return CSRC_OK;
+    g_last_hip = e;
+    return CSRC_ERR_HIP;
+}
+}  // namespace csrc
+
+extern "C" int32_t csrc_last_hip_error(void) { return csrc::g_last_hip; }
+extern "C" const char *csrc_last_hip_error_string(void)
+{
+    return hipGetErrorName(static_cast<hipError_t>(csrc::g_last_hip));
+}
 
 extern "C" const char *csrc_status_string(int s)
 {

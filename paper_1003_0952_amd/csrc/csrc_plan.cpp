@@ -46,6 +46,21 @@ void nnz_partition(int32_t n, const int32_t *ia, int32_t parts, std::vector<int3
     s[parts] = n;
 }
 
+// Split blocks of more than max_rows rows into m = ceil(rows/max_rows)
+// pieces at r0 + floor(p*rows/m): a tile keeps per-row state in LDS.
+void cap_tile_rows(std::vector<int32_t> &s, int32_t max_rows)
+{
+    std::vector<int32_t> out;
+    out.reserve(s.size());
+    out.push_back(s[0]);
+    for (size_t b = 0; b + 1 < s.size(); ++b) {
+        int64_t r0 = s[b], rows = (int64_t)s[b + 1] - r0;
+        int64_t m = std::max<int64_t>(1, (rows + max_rows - 1) / max_rows);
+        for (int64_t q = 1; q <= m; ++q) out.push_back((int32_t)(r0 + (q * rows) / m));
+    }
+    s.swap(out);
+}
+
 // Sorted distinct rows -> intervals, merging gaps of at most `gap` rows.
 void make_intervals(const std::vector<int32_t> &rows, int32_t gap,
                     std::vector<std::pair<int32_t, int32_t>> &iv)
@@ -77,7 +92,7 @@ extern "C" int csrc_plan_opts_default(int32_t variant, csrc_plan_opts *o)
     o->variant = variant;
     o->tile_work = 0;
     o->lanes = 0;
-    o->block = 256;
+    o->block = 0;
     o->color_criterion = CSRC_COLOR_WRITE_SET;
     o->ydtype = CSRC_F32;
     o->compensated = 0;
@@ -88,7 +103,7 @@ extern "C" int csrc_plan_opts_default(int32_t variant, csrc_plan_opts *o)
 static int default_tile_work(int32_t variant)
 {
     switch (variant) {
-    case CSRC_V_ATOMIC: return 4096;
+    case CSRC_V_ATOMIC: return 8192;
     case CSRC_V_PRIVATE: return 8192;
     case CSRC_V_OWNER: return 16384;
     default: return 4096;
@@ -114,7 +129,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         p->k = n ? ia[n] : 0;
         p->vdtype = vdtype;
         p->o = o;
-        if (p->o.block == 0) p->o.block = 256;
+        if (p->o.block == 0)
+            p->o.block = (o.variant == CSRC_V_PLAIN || o.variant == CSRC_V_COLOR) ? 256 : 512;
         if (p->o.lanes == 0) p->o.lanes = auto_lanes(n, p->k);
         if (p->o.lanes == 1) p->o.lanes = 2;
         if (p->o.tile_work == 0) p->o.tile_work = default_tile_work(o.variant);
@@ -129,9 +145,18 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             int64_t parts = std::max<int64_t>(1, (total + p->o.tile_work - 1) / p->o.tile_work);
             if (parts > (int64_t)1 << 30) { delete p; return CSRC_ERR_TOO_LARGE; }
             nnz_partition(n, ia, (int32_t)parts, p->tiles);
-            p->ntiles = (int32_t)parts;
-            for (int32_t t = 0; t < p->ntiles; ++t)
+            cap_tile_rows(p->tiles, csrc::kMaxTileRows);
+            p->ntiles = (int32_t)p->tiles.size() - 1;
+            p->tile_k.resize(p->tiles.size());
+            for (size_t t = 0; t < p->tiles.size(); ++t) p->tile_k[t] = ia[p->tiles[t]];
+            for (int32_t t = 0; t < p->ntiles; ++t) {
                 p->max_tile_rows = std::max(p->max_tile_rows, p->tiles[t + 1] - p->tiles[t]);
+                p->max_tile_entries = std::max(p->max_tile_entries, ia[p->tiles[t + 1]] - ia[p->tiles[t]]);
+            }
+            if (v == CSRC_V_ATOMIC) {
+                p->lds_bytes = csrc::lds_atomic(p->max_tile_rows, p->max_tile_entries, acc);
+                if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
+            }
         }
 
         if (v == CSRC_V_PRIVATE && n > 0) {
@@ -189,8 +214,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 int32_t b1 = (p->iv_row[g] + p->iv_len[g] - 1) / csrc::kMergeBlock;
                 for (int32_t b = b0; b <= b1; ++b) p->mb_iv[fill[b]++] = g;
             }
-            p->lds_bytes = (int64_t)(p->max_tile_rows + 1) * 4 + (int64_t)p->max_tile_rows * 2 * acc +
-                           (int64_t)p->max_window * 2 * acc + (int64_t)(p->max_intervals + 1) * 8 + 64;
+            p->lds_bytes = csrc::lds_private(p->max_tile_rows, p->max_window, p->max_tile_entries,
+                                             p->max_intervals, acc);
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 
@@ -217,8 +242,19 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 make_intervals(pull[t], 4, iv);
                 int32_t w = 0;
                 for (auto &e : iv) {
-                    p->iv_row.push_back(e.first);
-                    p->iv_len.push_back(e.second);
+                    // cut into chunks of at most kPullRows rows / kPullEntries
+                    // entries (a single longer row stays one chunk)
+                    int32_t a = e.first, end = e.first + e.second;
+                    while (a < end) {
+                        int32_t b = a + 1;
+                        while (b < end && b - a < csrc::kPullRows &&
+                               ia[b + 1] - ia[a] <= csrc::kPullEntries) ++b;
+                        p->iv_row.push_back(a);
+                        p->iv_len.push_back(b - a);
+                        p->max_pull_rows = std::max(p->max_pull_rows, b - a);
+                        p->max_pull_entries = std::max(p->max_pull_entries, ia[b] - ia[a]);
+                        a = b;
+                    }
                     w += e.second;
                 }
                 p->pulled_rows += w;
@@ -227,7 +263,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 p->max_intervals = std::max(p->max_intervals, (int32_t)iv.size());
                 std::vector<int32_t>().swap(pull[t]);
             }
-            p->lds_bytes = (int64_t)(p->max_tile_rows + 1) * 4 + (int64_t)p->max_tile_rows * 2 * acc + 64;
+            p->lds_bytes = csrc::lds_owner(p->max_tile_rows, p->max_pull_rows,
+                                           std::max(p->max_tile_entries, p->max_pull_entries), acc);
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 
@@ -245,6 +282,7 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
 
         // workspace image
         put(blob, p->t_tiles, p->tiles);
+        put(blob, p->t_tile_k, p->tile_k);
         put(blob, p->t_iv_ptr, p->iv_ptr);
         put(blob, p->t_iv_row, p->iv_row);
         put(blob, p->t_iv_len, p->iv_len);
@@ -280,11 +318,11 @@ extern "C" int csrc_plan_upload(const csrc_plan *p, void *ws, int64_t bytes, voi
     if (p->ws_bytes == 0) return CSRC_OK;
     if (!ws || bytes < p->ws_bytes) return CSRC_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(ws, p->blob.data(), (size_t)p->blob_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-        return CSRC_ERR_HIP;
+    int st = csrc::hip_status(hipMemcpyAsync(ws, p->blob.data(), (size_t)p->blob_bytes,
+                                             hipMemcpyHostToDevice, s));
+    if (st) return st;
     // the host image stays owned by the plan; wait so callers may reuse it freely
-    if (hipStreamSynchronize(s) != hipSuccess) return CSRC_ERR_HIP;
-    return CSRC_OK;
+    return csrc::hip_status(hipStreamSynchronize(s));
 }
 
 extern "C" int csrc_plan_get_info(const csrc_plan *p, csrc_plan_info *info)

@@ -122,30 +122,239 @@ __global__ __launch_bounds__(256) void k_plain(int32_t n, const int32_t *__restr
     atomic_add(&y[i], (YT)t);
 }
 
+// ------------------------------------------------------- flat tile engine
+//
+// The tile kernels stream the stored entries of a row block [r0, r1), i.e.
+// entries [k0, k1) = [ia[r0], ia[r1]).  A batch covers 4B consecutive
+// entries (B = workgroup size); lane l owns the pairs at 2l and 2B + 2l, so
+// every load instruction (ja as 8 bytes, al and au as 2 values) reads one
+// contiguous span across the wave.  Loads are non-temporal where the data is
+// read once.  The stream is software pipelined: the next batch's loads are
+// in flight while the current batch is processed.  The row of each entry
+// comes from an LDS table of uint16 row ids (relative to the block) filled
+// from ia; a lane's partial row sums are flushed into LDS when the row
+// changes.
+
+typedef int i2v __attribute__((ext_vector_type(2)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+constexpr uint32_t kNoRow = 0xFFFF;
+
+template <bool NT, class T>
+__device__ __forceinline__ T vload(const T *p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+// two consecutive entries starting at q (q even); elements at or past kend
+// are not read (zero)
+template <bool NT>
+__device__ __forceinline__ void pair(const int32_t *p, int64_t q, int64_t kend, int (&o)[2])
+{
+    if (q + 1 < kend) {
+        i2v v = vload<NT>(reinterpret_cast<const i2v *>(p + q));
+        o[0] = v.x; o[1] = v.y;
+    } else {
+        o[0] = q < kend ? p[q] : 0;
+        o[1] = 0;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void pair(const double *p, int64_t q, int64_t kend, double (&o)[2])
+{
+    if (q + 1 < kend) {
+        d2v v = vload<NT>(reinterpret_cast<const d2v *>(p + q));
+        o[0] = v.x; o[1] = v.y;
+    } else {
+        o[0] = q < kend ? p[q] : 0.0;
+        o[1] = 0.0;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void pair(const float *p, int64_t q, int64_t kend, float (&o)[2])
+{
+    if (q + 1 < kend) {
+        f2v v = vload<NT>(reinterpret_cast<const f2v *>(p + q));
+        o[0] = v.x; o[1] = v.y;
+    } else {
+        o[0] = q < kend ? p[q] : 0.f;
+        o[1] = 0.f;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void pair(const uint16_t *p, int64_t q, int64_t kend, float (&o)[2])
+{
+    if (q + 1 < kend) {
+        const uint32_t v = vload<NT>(reinterpret_cast<const uint32_t *>(p + q));
+        o[0] = __uint_as_float(v << 16);
+        o[1] = __uint_as_float(v & 0xFFFF0000u);
+    } else {
+        o[0] = q < kend ? ldv(p, q) : 0.f;
+        o[1] = 0.f;
+    }
+}
+
+// Fill s_rid[q - kb] = row - ra for the entries of rows [ra, rb), i.e.
+// [ia[ra], ia[rb]), and kNoRow on [kb, ia[ra]) and on [ia[rb], round2(...) + 2)
+// so every pair read of the stream finds a defined value.  kb is ia[ra]
+// rounded down to even.
+__device__ __forceinline__ void fill_row_ids(const int32_t *__restrict__ ia, int ra, int rb, int kb,
+                                            uint16_t *s_rid)
+{
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int k0 = ia[ra], k1 = ia[rb];
+    const int len = ((k1 - kb) + 3) & ~1;
+    for (int s = tid; s < k0 - kb; s += B) s_rid[s] = kNoRow;
+    for (int s = (k1 - kb) + tid; s < len; s += B) s_rid[s] = kNoRow;
+    for (int i = tid; i < rb - ra; i += B) {
+        const int q0 = ia[ra + i], q1 = ia[ra + i + 1];
+        for (int q = q0; q < q1; ++q) s_rid[q - kb] = (uint16_t)i;
+    }
+}
+
+// One lane's share of a batch: pairs at qb and qb + 2B.
+// LOAD_AL / LOAD_AU select which value arrays are fetched up front.
+template <class VT, bool LOAD_AL, bool LOAD_AU, bool NT>
+struct Batch {
+    using A = typename VT::A;
+    using V = typename VT::V;
+    int j[2][2];
+    A a[2][2];
+    A u[2][2];
+
+    __device__ __forceinline__ void load(int qb, int k1, int64_t kend, const int32_t *__restrict__ ja,
+                                         const V *__restrict__ al, const V *__restrict__ au)
+    {
+        const int half = 2 * (int)blockDim.x;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int q = qb + half * s;
+            if (q < k1) {
+                pair<NT>(ja, q, kend, j[s]);
+                if (LOAD_AL) pair<NT>(al, q, kend, a[s]);
+                if (LOAD_AU) pair<NT>(au, q, kend, u[s]);
+            } else {
+                j[s][0] = j[s][1] = -1;
+                a[s][0] = a[s][1] = A(0);
+                u[s][0] = u[s][1] = A(0);
+            }
+        }
+    }
+};
+
+// Stream entries [kb, k1) of the block (kb = k0 rounded down to even).  `cur`
+// holds the first batch, issued by the caller before its staging.  For each
+// entry of row r (relative) with column j: x_j = ent(j, au * s_x[r]) scatters
+// and gathers, and a lane's run of gathered products of one row goes to
+// flush(r, sum).  With LOAD_AU false, an au pair is fetched only if need_au(j)
+// holds for one of its entries (else its products are zero and ent ignores
+// them).
+template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush>
+__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, int kb, int k1, int64_t kend,
+                                           const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
+                                           const int32_t *__restrict__ ja,
+                                           const typename VT::V *__restrict__ al,
+                                           const typename VT::V *__restrict__ au, NeedAu need_au,
+                                           Ent ent, Flush flush)
+{
+    using A = typename VT::A;
+    const int half = 2 * (int)blockDim.x;
+    for (int qb = kb + 2 * (int)threadIdx.x; qb < k1; qb += 2 * half) {
+        Batch<VT, true, LOAD_AU, NT> nxt;
+        if (qb + 2 * half < k1) nxt.load(qb + 2 * half, k1, kend, ja, al, au);
+        uint32_t rv[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int q = qb + half * s;
+            rv[s] = q < k1 ? *reinterpret_cast<const uint32_t *>(s_rid + (q - kb)) : 0xFFFFFFFFu;
+        }
+        if (!LOAD_AU) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const bool need = ((rv[s] & 0xFFFF) != kNoRow && need_au(cur.j[s][0])) ||
+                                  ((rv[s] >> 16) != kNoRow && need_au(cur.j[s][1]));
+                if (need) pair<NT>(au, qb + half * s, kend, cur.u[s]);
+                else cur.u[s][0] = cur.u[s][1] = A(0);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
+            A g0 = A(0), g1 = A(0);
+            if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * s_x[r0]);
+            if (r1 != (int)kNoRow) g1 = cur.a[s][1] * ent(cur.j[s][1], cur.u[s][1] * s_x[r1]);
+            if (r0 == r1) {
+                if (r0 != (int)kNoRow) flush(r0, g0 + g1);
+            } else {
+                if (r0 != (int)kNoRow) flush(r0, g0);
+                if (r1 != (int)kNoRow) flush(r1, g1);
+            }
+        }
+        cur = nxt;
+    }
+}
+
+// Stage a tile's own rows: s_x[i] = x_i and s_y[i] = ad_i x_i (the diagonal
+// term starts every row sum).
+template <class VT>
+__device__ __forceinline__ void stage_rows(int r0, int T, const typename VT::V *__restrict__ ad,
+                                           const typename VT::X *__restrict__ x, typename VT::A *s_x,
+                                           typename VT::A *s_y)
+{
+    using A = typename VT::A;
+    for (int i = threadIdx.x; i < T; i += blockDim.x) {
+        const A xv = (A)x[r0 + i];
+        s_x[i] = xv;
+        s_y[i] = (A)ldv(ad, r0 + i) * xv;
+    }
+}
+
 // ----------------------------------------------------------------- ATOMIC
 
-template <int G, class VT, class YT>
+// Atomic scatter (Sec. 3 lists atomic primitives as the direct fix of the
+// race): y cleared first; scatters into the tile's own rows and the row sums
+// meet in LDS, every scatter below the tile is a global atomic add, and each
+// own row is added to y with one global atomic at the end.
+template <class VT, class YT>
 __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tiles,
+                                                const int32_t *__restrict__ tile_k, int64_t kend,
                                                 const int32_t *__restrict__ ia,
                                                 const int32_t *__restrict__ ja,
                                                 const typename VT::V *__restrict__ ad,
                                                 const typename VT::V *__restrict__ al,
                                                 const typename VT::V *__restrict__ au,
                                                 const typename VT::X *__restrict__ x,
-                                                YT *__restrict__ y)
+                                                YT *__restrict__ y, int tmax)
 {
     using A = typename VT::A;
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    int r0 = tiles[t], r1 = tiles[t + 1];
-    int lg = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
-    rows_loop<G, typename VT::V, A>(
-        r0, r1, grp, ngrp, lg, [](int i) { return i; }, [&](int r) { return ia[r]; },
-        [&](int r) { return (A)x[r]; }, [&](int r) { return (A)ldv(ad, r); }, ja, al, au,
-        [&](int j, A a, A w) -> A {
+    extern __shared__ __align__(16) unsigned char lds[];
+    A *s_x = reinterpret_cast<A *>(lds);
+    A *s_y = s_x + tmax;
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16(2 * (int64_t)tmax * sizeof(A)));
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r0 = tiles[t], r1 = tiles[t + 1], T = r1 - r0;
+    const int k0 = tile_k[t], k1 = tile_k[t + 1], kb = k0 & ~1;
+    Batch<VT, true, true, true> first;
+    first.load(kb + 2 * tid, k1, kend, ja, al, au);
+    stage_rows<VT>(r0, T, ad, x, s_x, s_y);
+    fill_row_ids(ia, r0, r1, kb, s_rid);
+    __syncthreads();
+    own_stream<VT, true, true>(
+        first, kb, k1, kend, s_rid, s_x, ja, al, au, [](int) { return true; },
+        [&](int j, A w) -> A {
+            if (j >= r0) {
+                atomic_add(&s_y[j - r0], w);
+                return s_x[j - r0];
+            }
             atomic_add(&y[j], (YT)w);
-            return a * (A)x[j];
+            return (A)x[j];
         },
-        [&](int r, A v) { atomic_add(&y[r], (YT)v); });
+        [&](int r, A v) { atomic_add(&s_y[r], v); });
+    __syncthreads();
+    for (int i = tid; i < T; i += B) atomic_add(&y[r0 + i], (YT)s_y[i]);
 }
 
 // ---------------------------------------------------------------- PRIVATE
@@ -154,14 +363,14 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
 // its own rows (s_y) and its effective range below r0 (s_w, compact window
 // slots).  x of both ranges is staged in LDS first (s_x, s_xw).  Own rows go
 // to y; window slots go to the partial buffer for the merge pass.
-template <int G, class VT, class YT>
-__global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__restrict__ ia,
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
                                                  const typename VT::V *__restrict__ ad,
                                                  const typename VT::V *__restrict__ al,
                                                  const typename VT::V *__restrict__ au,
                                                  const typename VT::X *__restrict__ x,
-                                                 YT *__restrict__ y, int tmax, int wmax, int ivmax)
+                                                 YT *__restrict__ y, int tmax, int wmax, int emax)
 {
     using A = typename VT::A;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -169,55 +378,53 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__res
     A *s_y = s_x + tmax;
     A *s_xw = s_y + tmax;
     A *s_w = s_xw + wmax;
-    int32_t *s_ia = reinterpret_cast<int32_t *>(s_w + wmax);
-    int32_t *s_ivrow = s_ia + tmax + 1;
-    int32_t *s_ivslot = s_ivrow + ivmax;
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + 2 * wmax) * sizeof(A)));
+    int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
+                                                   align16(((int64_t)emax + 4) * 2));
 
     const int tid = threadIdx.x, B = blockDim.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
-    const int e0 = P.iv_ptr[t], NI = P.iv_ptr[t + 1] - e0;
-    const int W = NI ? P.iv_slot[e0 + NI - 1] + P.iv_len[e0 + NI - 1] : 0;
+    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
+    Batch<VT, true, true, true> first;
+    first.load(kb + 2 * tid, k1, kend, ja, al, au);
 
-    for (int i = tid; i < T; i += B) {
-        s_ia[i] = ia[r0 + i];
-        s_x[i] = (A)x[r0 + i];
-        s_y[i] = A(0);
-    }
-    if (tid == 0) s_ia[T] = ia[r1];
+    const int e0 = P.iv_ptr[t], NI = P.iv_ptr[t + 1] - e0;
+    int32_t *s_ivslot = s_ivrow + NI;
+    const int W = NI ? P.iv_slot[e0 + NI - 1] + P.iv_len[e0 + NI - 1] : 0;
+    stage_rows<VT>(r0, T, ad, x, s_x, s_y);
     for (int i = tid; i < NI; i += B) {
         s_ivrow[i] = P.iv_row[e0 + i];
         s_ivslot[i] = P.iv_slot[e0 + i];
     }
+    fill_row_ids(ia, r0, r1, kb, s_rid);
     __syncthreads();
-    for (int s = tid; s < W; s += B) {
-        int k = upper_index(s_ivslot, NI, s);
-        s_xw[s] = (A)x[s_ivrow[k] + (s - s_ivslot[k])];
-        s_w[s] = A(0);
+    for (int sl = tid; sl < W; sl += B) {
+        const int k = upper_index(s_ivslot, NI, sl);
+        s_xw[sl] = (A)x[s_ivrow[k] + (sl - s_ivslot[k])];
+        s_w[sl] = A(0);
     }
     __syncthreads();
 
-    const int lg = tid % G, grp = tid / G, ngrp = B / G;
-    rows_loop<G, typename VT::V, A>(
-        r0, r1, grp, ngrp, lg, [](int i) { return i; }, [&](int r) { return s_ia[r - r0]; },
-        [&](int r) { return s_x[r - r0]; }, [&](int r) { return (A)ldv(ad, r); }, ja, al, au,
-        [&](int j, A a, A w) -> A {
+    own_stream<VT, true, true>(
+        first, kb, k1, kend, s_rid, s_x, ja, al, au, [](int) { return true; },
+        [&](int j, A w) -> A {
             if (j >= r0) {
                 atomic_add(&s_y[j - r0], w);
-                return a * s_x[j - r0];
+                return s_x[j - r0];
             }
-            int k = upper_index(s_ivrow, NI, j);
-            int sl = s_ivslot[k] + (j - s_ivrow[k]);
+            const int k = upper_index(s_ivrow, NI, j);
+            const int sl = s_ivslot[k] + (j - s_ivrow[k]);
             atomic_add(&s_w[sl], w);
-            return a * s_xw[sl];
+            return s_xw[sl];
         },
-        [&](int r, A v) { atomic_add(&s_y[r - r0], v); });
+        [&](int r, A v) { atomic_add(&s_y[r], v); });
     __syncthreads();
 
     for (int i = tid; i < T; i += B) y[r0 + i] = (YT)s_y[i];
     if (W) {
         A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0];
-        for (int s = tid; s < W; s += B) part[s] = s_w[s];
+        for (int sl = tid; sl < W; sl += B) part[sl] = s_w[sl];
     }
 }
 
@@ -233,13 +440,13 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(int32_t n, PlanDev P, YT 
     const A *part = reinterpret_cast<const A *>(P.partials);
     MT s = (MT)y[i], c = MT(0);
     for (int e = e0; e < e1; ++e) {
-        int g = P.mb_iv[e];
-        int a = P.iv_row[g], L = P.iv_len[g];
+        const int g = P.mb_iv[e];
+        const int a = P.iv_row[g], L = P.iv_len[g];
         if (i >= a && i < a + L) {
-            MT v = (MT)part[P.iv_goff[g] + (i - a)];
+            const MT v = (MT)part[P.iv_goff[g] + (i - a)];
             if (COMP) {
-                MT s2 = s + v;
-                MT bp = s2 - s;
+                const MT s2 = s + v;
+                const MT bp = s2 - s;
                 c += (s - (s2 - bp)) + (v - bp);
                 s = s2;
             } else {
@@ -252,73 +459,78 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(int32_t n, PlanDev P, YT 
 
 // ------------------------------------------------------------------ OWNER
 
-// Owner computes: the tile's own rows gather (out-of-tile x from L2) and
-// scatter only into the tile; then the tile visits the rows of later tiles
-// that scatter into it (pull intervals) and adds those contributions.  Each
-// y entry is completed in one workgroup's LDS and stored once.
-template <int G, class VT, class YT>
-__global__ __launch_bounds__(512) void k_owner(PlanDev P, const int32_t *__restrict__ ia,
+// Owner computes: the tile streams its own rows, gathering x from LDS or L2
+// and scattering only into its own rows; then it visits, chunk by chunk, the
+// rows of later tiles that scatter into it (pull chunks, re-read from cache:
+// temporal loads) and adds the entries whose target lies in [r0, r1).  Each y
+// entry is completed in one workgroup's LDS and stored once: no partials, no
+// atomics outside LDS, no second pass.
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_owner(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
                                                const int32_t *__restrict__ ja,
                                                const typename VT::V *__restrict__ ad,
                                                const typename VT::V *__restrict__ al,
                                                const typename VT::V *__restrict__ au,
                                                const typename VT::X *__restrict__ x,
-                                               YT *__restrict__ y, int tmax)
+                                               YT *__restrict__ y, int tmax, int pmax, int emax)
 {
     using A = typename VT::A;
-    using V = typename VT::V;
     extern __shared__ __align__(16) unsigned char lds[];
     A *s_x = reinterpret_cast<A *>(lds);
     A *s_y = s_x + tmax;
-    int32_t *s_ia = reinterpret_cast<int32_t *>(s_y + tmax);
+    A *s_xp = s_y + tmax;
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + pmax) * sizeof(A)));
 
     const int tid = threadIdx.x, B = blockDim.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
-    for (int i = tid; i < T; i += B) {
-        s_ia[i] = ia[r0 + i];
-        s_x[i] = (A)x[r0 + i];
-        s_y[i] = A(0);
-    }
-    if (tid == 0) s_ia[T] = ia[r1];
+    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
+    Batch<VT, true, false, false> first;
+    first.load(kb + 2 * tid, k1, kend, ja, al, au);
+    stage_rows<VT>(r0, T, ad, x, s_x, s_y);
+    fill_row_ids(ia, r0, r1, kb, s_rid);
     __syncthreads();
-
-    const int lg = tid % G, grp = tid / G, ngrp = B / G;
-    rows_loop<G, V, A>(
-        r0, r1, grp, ngrp, lg, [](int i) { return i; }, [&](int r) { return s_ia[r - r0]; },
-        [&](int r) { return s_x[r - r0]; }, [&](int r) { return (A)ldv(ad, r); }, ja, al, au,
-        [&](int j, A a, A w) -> A {
+    own_stream<VT, false, false>(
+        first, kb, k1, kend, s_rid, s_x, ja, al, au, [&](int j) { return j >= r0; },
+        [&](int j, A w) -> A {
             if (j >= r0) {
                 atomic_add(&s_y[j - r0], w);
-                return a * s_x[j - r0];
+                return s_x[j - r0];
             }
-            return a * (A)x[j];
+            return (A)x[j];
         },
-        [&](int r, A v) { atomic_add(&s_y[r - r0], v); });
+        [&](int r, A v) { atomic_add(&s_y[r], v); });
 
-    // pulled rows: only their entries with targets inside [r0, r1)
     const int p0 = P.iv_ptr[t], p1 = P.iv_ptr[t + 1];
+    const int half = 2 * B;
     for (int e = p0; e < p1; ++e) {
-        const int a0 = P.iv_row[e], L = P.iv_len[e];
-        for (int base = grp; base < L; base += kUnroll * ngrp) {
-            int q0[kUnroll], q1[kUnroll];
-            A xi[kUnroll];
+        const int pa = P.iv_row[e], L = P.iv_len[e];
+        const int qa = ia[pa], qe = ia[pa + L], qbase = qa & ~1;
+        Batch<VT, false, false, false> cur;
+        cur.load(qbase + 2 * tid, qe, kend, ja, al, au);
+        __syncthreads();   // earlier readers of s_rid / s_xp are done
+        for (int i = tid; i < L; i += B) s_xp[i] = (A)x[pa + i];
+        fill_row_ids(ia, pa, pa + L, qbase, s_rid);
+        __syncthreads();
+        for (int qb = qbase + 2 * tid; qb < qe; qb += 2 * half) {
+            Batch<VT, false, false, false> nxt;
+            if (qb + 2 * half < qe) nxt.load(qb + 2 * half, qe, kend, ja, al, au);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                int idx = base + u * ngrp;
-                bool ok = idx < L;
-                int r = a0 + idx;
-                q0[u] = ok ? ia[r] : 0;
-                q1[u] = ok ? ia[r + 1] : 0;
-                xi[u] = ok ? (A)x[r] : A(0);
+            for (int s = 0; s < 2; ++s) {
+                const int q = qb + half * s;
+                if (q >= qe) continue;
+                const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - qbase));
+                const int ra = (int)(rv & 0xFFFF), rb = (int)(rv >> 16);
+                const int j0 = cur.j[s][0], j1 = cur.j[s][1];
+                const bool t0 = ra != (int)kNoRow && j0 >= r0 && j0 < r1;
+                const bool t1 = rb != (int)kNoRow && j1 >= r0 && j1 < r1;
+                if (!(t0 || t1)) continue;
+                A uv[2];
+                pair<false>(au, q, kend, uv);
+                if (t0) atomic_add(&s_y[j0 - r0], uv[0] * s_xp[ra]);
+                if (t1) atomic_add(&s_y[j1 - r0], uv[1] * s_xp[rb]);
             }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                for (int q = q0[u] + lg; q < q1[u]; q += G) {
-                    int j = ja[q];
-                    if (j >= r0 && j < r1) atomic_add(&s_y[j - r0], (A)ldv(au, q) * xi[u]);
-                }
-            }
+            cur = nxt;
         }
     }
     __syncthreads();
@@ -361,6 +573,7 @@ static PlanDev plan_dev(const csrc_plan *p, void *ws)
     auto at = [&](const Table &t) -> const void * { return b ? b + t.offset : nullptr; };
     PlanDev d;
     d.tiles = (const int32_t *)at(p->t_tiles);
+    d.tile_k = (const int32_t *)at(p->t_tile_k);
     d.iv_ptr = (const int32_t *)at(p->t_iv_ptr);
     d.iv_row = (const int32_t *)at(p->t_iv_row);
     d.iv_len = (const int32_t *)at(p->t_iv_len);
@@ -396,17 +609,25 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
         k_plain<VT, YT><<<(n + 255) / 256, 256, 0, s>>>(n, A->ia, A->ja, ad, al, au, x, y);
         break;
-    case CSRC_V_ATOMIC:
+    case CSRC_V_ATOMIC: {
         k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
-        k_atomic<G, VT, YT><<<p->ntiles, B, 0, s>>>(P.tiles, A->ia, A->ja, ad, al, au, x, y);
+        const int tmax = p->max_tile_rows;
+        const size_t lds = (size_t)lds_atomic(tmax, p->max_tile_entries, sizeof(Acc));
+        auto kern = k_atomic<VT, YT>;
+        if (lds > 65536 &&
+            hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
+            return CSRC_ERR_HIP;
+        kern<<<p->ntiles, B, lds, s>>>(P.tiles, P.tile_k, A->k, A->ia, A->ja, ad, al, au, x, y, tmax);
         break;
+    }
     case CSRC_V_PRIVATE: {
-        int tmax = p->max_tile_rows, wmax = p->max_window, ivmax = p->max_intervals;
-        size_t lds = (size_t)(2 * tmax + 2 * wmax) * sizeof(Acc) + (size_t)(tmax + 1 + 2 * ivmax + 1) * 4;
-        auto kern = k_private<G, VT, YT>;
-        if (lds > 65536)
-            hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        kern<<<p->ntiles, B, lds, s>>>(P, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, ivmax);
+        const int tmax = p->max_tile_rows, wmax = p->max_window, emax = p->max_tile_entries;
+        const size_t lds = (size_t)lds_private(tmax, wmax, emax, p->max_intervals, sizeof(Acc));
+        auto kern = k_private<VT, YT>;
+        if (lds > 65536 &&
+            hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
+            return CSRC_ERR_HIP;
+        kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, emax);
         if (p->nmerge_blocks > 0 && p->window_slots > 0) {
             if (std::is_same<YT, double>::value)
                 k_merge<Acc, YT, double, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
@@ -418,12 +639,14 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         break;
     }
     case CSRC_V_OWNER: {
-        int tmax = p->max_tile_rows;
-        size_t lds = (size_t)(2 * tmax) * sizeof(Acc) + (size_t)(tmax + 1) * 4;
-        auto kern = k_owner<G, VT, YT>;
-        if (lds > 65536)
-            hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        kern<<<p->ntiles, B, lds, s>>>(P, A->ia, A->ja, ad, al, au, x, y, tmax);
+        const int tmax = p->max_tile_rows, pmax = p->max_pull_rows;
+        const int emax = std::max(p->max_tile_entries, p->max_pull_entries);
+        const size_t lds = (size_t)lds_owner(tmax, pmax, emax, sizeof(Acc));
+        auto kern = k_owner<VT, YT>;
+        if (lds > 65536 &&
+            hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
+            return CSRC_ERR_HIP;
+        kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, pmax, emax);
         break;
     }
     case CSRC_V_COLOR: {
@@ -439,7 +662,7 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
     default:
         return CSRC_ERR_ARG;
     }
-    return hipGetLastError() == hipSuccess ? CSRC_OK : CSRC_ERR_HIP;
+    return hip_status(hipGetLastError());
 }
 
 template <class VT, class YT>
@@ -472,6 +695,10 @@ int check_call(const csrc_matrix *A, const csrc_plan *p, void *ws, int64_t ws_by
     if (A->n != p->n || A->k != p->k || A->vdtype != p->vdtype) return CSRC_ERR_PLAN;
     if (A->n > 0 && (!A->ia || !A->ad || (A->k > 0 && (!A->ja || !A->al || !A->au)))) return CSRC_ERR_ARG;
     if (p->ws_bytes > 0 && (!ws || ws_bytes < p->ws_bytes)) return CSRC_ERR_WORKSPACE;
+    // the tile kernels read ja/al/au with 16-byte (8-byte for bfloat16) vector loads
+    const uintptr_t va = A->vdtype == CSRC_BF16 ? 8 : 16;
+    if (A->k > 0 && (((uintptr_t)A->ja % 16) || ((uintptr_t)A->al % va) || ((uintptr_t)A->au % va)))
+        return CSRC_ERR_ARG;
     return CSRC_OK;
 }
 

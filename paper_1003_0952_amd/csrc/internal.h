@@ -19,6 +19,30 @@ inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
 inline int value_bytes(int32_t dt) { return dt == CSRC_F64 ? 8 : (dt == CSRC_F32 ? 4 : 2); }
 inline int acc_bytes(int32_t vdt) { return vdt == CSRC_F64 ? 8 : 4; }
+constexpr int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
+
+constexpr int kMaxTileRows = 2048;   // rows per tile (per-row state lives in LDS)
+constexpr int kPullRows = 1024;       // rows per pull chunk (OWNER)
+constexpr int kPullEntries = 16384;   // stored entries per pull chunk (OWNER)
+
+// Dynamic LDS of the flat tile kernels (acc = accumulator bytes).  Row ids
+// of a block's entries are uint16, padded by 4.
+//   PRIVATE: x, y of own rows; x, partial of window slots; row ids; window
+//            interval starts and slots
+//   OWNER:   x, y of own rows; x of pulled rows; row ids
+//   ATOMIC:  x, y of own rows; row ids
+inline int64_t lds_private(int64_t tmax, int64_t wmax, int64_t emax, int64_t ivmax, int acc)
+{
+    return align16((2 * tmax + 2 * wmax) * acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+}
+inline int64_t lds_owner(int64_t tmax, int64_t pmax, int64_t emax, int acc)
+{
+    return align16((2 * tmax + pmax) * acc) + align16((emax + 4) * 2);
+}
+inline int64_t lds_atomic(int64_t tmax, int64_t emax, int acc)
+{
+    return align16(2 * tmax * acc) + align16((emax + 4) * 2);
+}
 
 // A table placed in the device workspace.
 struct Table {
@@ -29,6 +53,7 @@ struct Table {
 // Device-side view of a single-matrix plan (all pointers into the workspace).
 struct PlanDev {
     const int32_t *tiles;      // ntiles+1 row boundaries
+    const int32_t *tile_k;     // ntiles+1: ia at each boundary (first entry)
     const int32_t *iv_ptr;     // ntiles+1: intervals of each tile
     const int32_t *iv_row;     // first row of each interval
     const int32_t *iv_len;     // rows in each interval
@@ -54,17 +79,20 @@ struct csrc_plan {
     int32_t max_tile_rows = 0;
     int32_t max_window = 0;     // PRIVATE: slots; OWNER: pulled rows
     int32_t max_intervals = 0;
+    int32_t max_tile_entries = 0;   // stored lower entries of the largest tile
+    int32_t max_pull_rows = 0;      // OWNER: rows of the largest pull chunk
+    int32_t max_pull_entries = 0;   // OWNER: entries of the largest pull chunk
     int64_t window_slots = 0;
     int64_t pulled_rows = 0;
     int64_t lds_bytes = 0;
     int32_t ncolors = 0;
     int32_t nmerge_blocks = 0;
     // host tables
-    std::vector<int32_t> tiles, iv_ptr, iv_row, iv_len, iv_slot, mb_ptr, mb_iv;
+    std::vector<int32_t> tiles, tile_k, iv_ptr, iv_row, iv_len, iv_slot, mb_ptr, mb_iv;
     std::vector<int64_t> iv_goff;
     std::vector<int32_t> color, crow, cptr;
     // layout of the workspace
-    csrc::Table t_tiles, t_iv_ptr, t_iv_row, t_iv_len, t_iv_slot, t_iv_goff,
+    csrc::Table t_tiles, t_tile_k, t_iv_ptr, t_iv_row, t_iv_len, t_iv_slot, t_iv_goff,
         t_mb_ptr, t_mb_iv, t_crow, t_partials;
     int64_t blob_bytes = 0;      // bytes of uploaded tables (prefix of workspace)
     int64_t ws_bytes = 0;
@@ -72,6 +100,9 @@ struct csrc_plan {
 };
 
 namespace csrc {
+// Records a failing HIP status for csrc_last_hip_error; returns CSRC_ERR_HIP
+// (or CSRC_OK when status is 0).
+int hip_status(int hip_error);
 // host helpers implemented in csrc_host.cpp
 int color_rows(int32_t n, const int32_t *ia, const int32_t *ja, int32_t criterion,
                int32_t *color, int32_t *ncolors);

@@ -152,7 +152,7 @@ def test_plan_tiles_match_partition(make, work):
     c, h = host_matrix(make())
     for variant in ("atomic", "private", "owner"):
         p = HostPlan(h, variant, tile_work=work)
-        assert np.array_equal(p.export(0), R.partition_for_target(c["ia"], work))
+        assert np.array_equal(p.export(0), R.partition_for_target(c["ia"], work, 2048))
 
 
 @pytest.mark.parametrize("make", MATS[:5])

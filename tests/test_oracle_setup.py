@@ -121,3 +121,12 @@ def test_out_of_tile_targets_brute_force():
                 if c["ja"][q] < r0:
                     expect.add(int(c["ja"][q]))
         assert list(R.out_of_tile_targets(c, r0, r1)) == sorted(expect)
+
+
+def test_row_cap():
+    bounds = np.array([0, 5, 5, 4100, 4200, 10000])
+    capped = R.cap_rows(bounds, 2048)
+    # 4095 rows -> 2 pieces, 5800 rows -> 3 pieces, the rest unchanged
+    assert list(capped) == [0, 5, 5, 5 + 4095 // 2, 4100, 4200, 4200 + 5800 // 3,
+                            4200 + 2 * 5800 // 3, 10000]
+    assert np.all(np.diff(capped) <= 2048) and np.all(np.diff(capped) >= 0)
