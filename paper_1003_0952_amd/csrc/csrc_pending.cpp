@@ -4,10 +4,6 @@
 
 extern "C" {
 
-int csrc_spmm(const csrc_matrix *, const csrc_plan *, int32_t, const void *, int64_t, void *, int64_t,
-              void *, int64_t, void *) { return CSRC_ERR_UNSUPPORTED; }
-int csrc_spmm_t(const csrc_matrix *, const csrc_plan *, int32_t, const void *, int64_t, void *,
-                int64_t, void *, int64_t, void *) { return CSRC_ERR_UNSUPPORTED; }
 int csrc_batch_plan_create(int32_t, const int32_t *, const int32_t *const *, const int32_t *const *,
                            const int32_t *, int32_t, const csrc_batch_opts *, csrc_batch_plan **)
 { return CSRC_ERR_UNSUPPORTED; }

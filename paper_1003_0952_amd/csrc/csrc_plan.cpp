@@ -133,7 +133,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             p->o.block = (o.variant == CSRC_V_PLAIN || o.variant == CSRC_V_COLOR) ? 256 : 512;
         if (p->o.lanes == 0) p->o.lanes = auto_lanes(n, p->k);
         if (p->o.lanes == 1) p->o.lanes = 2;
-        if (p->o.tile_work == 0) p->o.tile_work = default_tile_work(o.variant);
+        if (p->o.tile_work == 0)
+            p->o.tile_work = default_tile_work(o.variant) / (o.max_rhs > 1 ? 4 : 1);
         if (p->o.max_rhs == 0) p->o.max_rhs = 1;
         if (vdtype == CSRC_F64) p->o.ydtype = CSRC_F64;
         const int acc = csrc::acc_bytes(vdtype);
@@ -216,6 +217,10 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             }
             p->lds_bytes = csrc::lds_private(p->max_tile_rows, p->max_window, p->max_tile_entries,
                                              p->max_intervals, acc);
+            if (p->o.max_rhs > 1)
+                p->lds_bytes = std::max(p->lds_bytes,
+                                        csrc::lds_private_mm(p->max_tile_rows, p->max_window, p->max_tile_entries,
+                                                             p->max_intervals, acc, csrc::mm_columns(vdtype)));
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 
@@ -263,8 +268,11 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 p->max_intervals = std::max(p->max_intervals, (int32_t)iv.size());
                 std::vector<int32_t>().swap(pull[t]);
             }
-            p->lds_bytes = csrc::lds_owner(p->max_tile_rows, p->max_pull_rows,
-                                           std::max(p->max_tile_entries, p->max_pull_entries), acc);
+            const int64_t em = std::max(p->max_tile_entries, p->max_pull_entries);
+            p->lds_bytes = csrc::lds_owner(p->max_tile_rows, p->max_pull_rows, em, acc);
+            if (p->o.max_rhs > 1)
+                p->lds_bytes = std::max(p->lds_bytes, csrc::lds_owner_mm(p->max_tile_rows, p->max_pull_rows, em, acc,
+                                                                         csrc::mm_columns(vdtype)));
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 

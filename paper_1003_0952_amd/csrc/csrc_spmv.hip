@@ -106,20 +106,20 @@ __global__ __launch_bounds__(256) void k_plain(int32_t n, const int32_t *__restr
                                                const typename VT::V *__restrict__ ad,
                                                const typename VT::V *__restrict__ al,
                                                const typename VT::V *__restrict__ au,
-                                               const typename VT::X *__restrict__ x,
-                                               YT *__restrict__ y)
+                                               const typename VT::X *__restrict__ x, int64_t ldx,
+                                               YT *__restrict__ y, int64_t ldy)
 {
     using A = typename VT::A;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    A xi = (A)x[i];
+    A xi = (A)x[i * ldx];
     A t = (A)ldv(ad, i) * xi;
     for (int q = ia[i]; q < ia[i + 1]; ++q) {
         int j = ja[q];
-        t += (A)ldv(al, q) * (A)x[j];
-        atomic_add(&y[j], (YT)((A)ldv(au, q) * xi));
+        t += (A)ldv(al, q) * (A)x[j * ldx];
+        atomic_add(&y[j * ldy], (YT)((A)ldv(au, q) * xi));
     }
-    atomic_add(&y[i], (YT)t);
+    atomic_add(&y[i * ldy], (YT)t);
 }
 
 // ------------------------------------------------------- flat tile engine
@@ -301,11 +301,11 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, in
 template <class VT>
 __device__ __forceinline__ void stage_rows(int r0, int T, const typename VT::V *__restrict__ ad,
                                            const typename VT::X *__restrict__ x, typename VT::A *s_x,
-                                           typename VT::A *s_y)
+                                           typename VT::A *s_y, int64_t ldx = 1)
 {
     using A = typename VT::A;
     for (int i = threadIdx.x; i < T; i += blockDim.x) {
-        const A xv = (A)x[r0 + i];
+        const A xv = (A)x[(r0 + i) * ldx];
         s_x[i] = xv;
         s_y[i] = (A)ldv(ad, r0 + i) * xv;
     }
@@ -325,8 +325,8 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
                                                 const typename VT::V *__restrict__ ad,
                                                 const typename VT::V *__restrict__ al,
                                                 const typename VT::V *__restrict__ au,
-                                                const typename VT::X *__restrict__ x,
-                                                YT *__restrict__ y, int tmax)
+                                                const typename VT::X *__restrict__ x, int64_t ldx,
+                                                YT *__restrict__ y, int64_t ldy, int tmax)
 {
     using A = typename VT::A;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
     const int k0 = tile_k[t], k1 = tile_k[t + 1], kb = k0 & ~1;
     Batch<VT, true, true, true> first;
     first.load(kb + 2 * tid, k1, kend, ja, al, au);
-    stage_rows<VT>(r0, T, ad, x, s_x, s_y);
+    stage_rows<VT>(r0, T, ad, x, s_x, s_y, ldx);
     fill_row_ids(ia, r0, r1, kb, s_rid);
     __syncthreads();
     own_stream<VT, true, true>(
@@ -349,12 +349,12 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
                 atomic_add(&s_y[j - r0], w);
                 return s_x[j - r0];
             }
-            atomic_add(&y[j], (YT)w);
-            return (A)x[j];
+            atomic_add(&y[j * ldy], (YT)w);
+            return (A)x[j * ldx];
         },
         [&](int r, A v) { atomic_add(&s_y[r], v); });
     __syncthreads();
-    for (int i = tid; i < T; i += B) atomic_add(&y[r0 + i], (YT)s_y[i]);
+    for (int i = tid; i < T; i += B) atomic_add(&y[(r0 + i) * ldy], (YT)s_y[i]);
 }
 
 // ---------------------------------------------------------------- PRIVATE
@@ -537,6 +537,266 @@ __global__ __launch_bounds__(512) void k_owner(PlanDev P, int64_t kend, const in
     for (int i = tid; i < T; i += B) y[r0 + i] = (YT)s_y[i];
 }
 
+// ----------------------------------------------------- multiple right-hand sides
+//
+// Y = A X for row-major n x r blocks.  Each tile keeps C columns of its rows
+// (and of its window slots) in LDS at a time and streams its entries once per
+// chunk of C columns; every stored entry is applied to all C columns.  Chunks
+// after the first re-read the tile's entries from L2 (temporal loads).
+
+template <class VT> struct MmCols { static constexpr int C = 4; };
+template <> struct MmCols<F32T> { static constexpr int C = 8; };
+template <> struct MmCols<B16T> { static constexpr int C = 8; };
+
+// Process the C columns of one stored entry q of row r (relative) with column
+// j: gather into acc[], scatter au * x_r into the LDS slot scat[], gather x_j
+// from xj[] (both C-wide rows of LDS or, for xj, of global memory).
+template <int C, class A>
+__device__ __forceinline__ void mm_entry(A a, A u, const A *xr, const A *xj, A *scat, A (&acc)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        atomic_add(&scat[c], u * xr[c]);
+        acc[c] += a * xj[c];
+    }
+}
+
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_private_mm(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
+                                                    const int32_t *__restrict__ ja,
+                                                    const typename VT::V *__restrict__ ad,
+                                                    const typename VT::V *__restrict__ al,
+                                                    const typename VT::V *__restrict__ au,
+                                                    const typename VT::X *__restrict__ X, int64_t ldx,
+                                                    YT *__restrict__ Y, int64_t ldy, int r, int tmax,
+                                                    int wmax, int emax)
+{
+    using A = typename VT::A;
+    constexpr int C = MmCols<VT>::C;
+    extern __shared__ __align__(16) unsigned char lds[];
+    A *s_x = reinterpret_cast<A *>(lds);
+    A *s_y = s_x + (int64_t)tmax * C;
+    A *s_xw = s_y + (int64_t)tmax * C;
+    A *s_w = s_xw + (int64_t)wmax * C;
+    uint16_t *s_rid =
+        reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + 2 * wmax) * C * sizeof(A)));
+    int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
+                                                   align16(((int64_t)emax + 4) * 2));
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
+    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
+    const int e0 = P.iv_ptr[t], NI = P.iv_ptr[t + 1] - e0;
+    int32_t *s_ivslot = s_ivrow + NI;
+    const int W = NI ? P.iv_slot[e0 + NI - 1] + P.iv_len[e0 + NI - 1] : 0;
+    for (int i = tid; i < NI; i += B) {
+        s_ivrow[i] = P.iv_row[e0 + i];
+        s_ivslot[i] = P.iv_slot[e0 + i];
+    }
+    fill_row_ids(ia, r0, r1, kb, s_rid);
+    const int half = 2 * B;
+    for (int cc = 0; cc < r; cc += C) {
+        const int nc = min(C, r - cc);
+        __syncthreads();   // previous chunk's readers are done; tables are visible
+        for (int e = tid; e < T * C; e += B) {
+            const int i = e / C, c = e % C;
+            const A xv = c < nc ? (A)X[(int64_t)(r0 + i) * ldx + cc + c] : A(0);
+            s_x[e] = xv;
+            s_y[e] = (A)ldv(ad, r0 + i) * xv;
+        }
+        for (int e = tid; e < W * C; e += B) {
+            const int sl = e / C, c = e % C;
+            const int k = upper_index(s_ivslot, NI, sl);
+            s_xw[e] = c < nc ? (A)X[(int64_t)(s_ivrow[k] + (sl - s_ivslot[k])) * ldx + cc + c] : A(0);
+            s_w[e] = A(0);
+        }
+        __syncthreads();
+        Batch<VT, true, true, false> cur;
+        cur.load(kb + 2 * tid, k1, kend, ja, al, au);
+        for (int qb = kb + 2 * tid; qb < k1; qb += 2 * half) {
+            Batch<VT, true, true, false> nxt;
+            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, k1, kend, ja, al, au);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                const int q = qb + half * sp;
+                if (q >= k1) continue;
+                const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - kb));
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int row = (int)((rv >> (16 * h)) & 0xFFFF);
+                    if (row == (int)kNoRow) continue;
+                    const int j = cur.j[sp][h];
+                    A acc[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] = A(0);
+                    if (j >= r0) {
+                        mm_entry<C>(cur.a[sp][h], cur.u[sp][h], s_x + row * C, s_x + (j - r0) * C,
+                                    s_y + (j - r0) * C, acc);
+                    } else {
+                        const int k = upper_index(s_ivrow, NI, j);
+                        const int sl = s_ivslot[k] + (j - s_ivrow[k]);
+                        mm_entry<C>(cur.a[sp][h], cur.u[sp][h], s_x + row * C, s_xw + sl * C, s_w + sl * C,
+                                    acc);
+                    }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) atomic_add(&s_y[row * C + c], acc[c]);
+                }
+            }
+            cur = nxt;
+        }
+        __syncthreads();
+        for (int e = tid; e < T * C; e += B) {
+            const int i = e / C, c = e % C;
+            if (c < nc) Y[(int64_t)(r0 + i) * ldy + cc + c] = (YT)s_y[e];
+        }
+        if (W) {
+            A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0] * r;
+            for (int e = tid; e < W * C; e += B) {
+                const int sl = e / C, c = e % C;
+                if (c < nc) part[(int64_t)sl * r + cc + c] = s_w[e];
+            }
+        }
+    }
+}
+
+// Merge pass for r columns: Y[i, c] += partial slots covering row i, in
+// ascending tile order; partial slot g of a tile holds r values.
+template <class A, class YT, class MT, bool COMP>
+__global__ __launch_bounds__(kMergeBlock) void k_merge_mm(int32_t n, PlanDev P, YT *__restrict__ Y,
+                                                          int64_t ldy, int r)
+{
+    const int b = blockIdx.x;
+    const int e0 = P.mb_ptr[b], e1 = P.mb_ptr[b + 1];
+    if (e0 == e1) return;
+    const A *part = reinterpret_cast<const A *>(P.partials);
+    for (int e = threadIdx.x; e < kMergeBlock * r; e += blockDim.x) {
+        const int i = b * kMergeBlock + e / r, c = e % r;
+        if (i >= n) break;
+        MT s = (MT)Y[(int64_t)i * ldy + c], cm = MT(0);
+        for (int g_ = e0; g_ < e1; ++g_) {
+            const int g = P.mb_iv[g_];
+            const int a = P.iv_row[g], L = P.iv_len[g];
+            if (i >= a && i < a + L) {
+                const MT v = (MT)part[(P.iv_goff[g] + (i - a)) * r + c];
+                if (COMP) {
+                    const MT s2 = s + v;
+                    const MT bp = s2 - s;
+                    cm += (s - (s2 - bp)) + (v - bp);
+                    s = s2;
+                } else {
+                    s += v;
+                }
+            }
+        }
+        Y[(int64_t)i * ldy + c] = (YT)(s + cm);
+    }
+}
+
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_owner_mm(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
+                                                  const int32_t *__restrict__ ja,
+                                                  const typename VT::V *__restrict__ ad,
+                                                  const typename VT::V *__restrict__ al,
+                                                  const typename VT::V *__restrict__ au,
+                                                  const typename VT::X *__restrict__ X, int64_t ldx,
+                                                  YT *__restrict__ Y, int64_t ldy, int r, int tmax, int pmax,
+                                                  int emax)
+{
+    using A = typename VT::A;
+    constexpr int C = MmCols<VT>::C;
+    extern __shared__ __align__(16) unsigned char lds[];
+    A *s_x = reinterpret_cast<A *>(lds);
+    A *s_y = s_x + (int64_t)tmax * C;
+    A *s_xp = s_y + (int64_t)tmax * C;
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + pmax) * C * sizeof(A)));
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
+    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
+    const int half = 2 * B;
+    const int p0 = P.iv_ptr[t], p1 = P.iv_ptr[t + 1];
+    for (int cc = 0; cc < r; cc += C) {
+        const int nc = min(C, r - cc);
+        __syncthreads();
+        for (int e = tid; e < T * C; e += B) {
+            const int i = e / C, c = e % C;
+            const A xv = c < nc ? (A)X[(int64_t)(r0 + i) * ldx + cc + c] : A(0);
+            s_x[e] = xv;
+            s_y[e] = (A)ldv(ad, r0 + i) * xv;
+        }
+        fill_row_ids(ia, r0, r1, kb, s_rid);
+        __syncthreads();
+        Batch<VT, true, true, false> cur;
+        cur.load(kb + 2 * tid, k1, kend, ja, al, au);
+        for (int qb = kb + 2 * tid; qb < k1; qb += 2 * half) {
+            Batch<VT, true, true, false> nxt;
+            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, k1, kend, ja, al, au);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                const int q = qb + half * sp;
+                if (q >= k1) continue;
+                const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - kb));
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int row = (int)((rv >> (16 * h)) & 0xFFFF);
+                    if (row == (int)kNoRow) continue;
+                    const int j = cur.j[sp][h];
+                    const A a = cur.a[sp][h], u = cur.u[sp][h];
+                    if (j >= r0) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            atomic_add(&s_y[(j - r0) * C + c], u * s_x[row * C + c]);
+                            atomic_add(&s_y[row * C + c], a * s_x[(j - r0) * C + c]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            const A xj = c < nc ? (A)X[(int64_t)j * ldx + cc + c] : A(0);
+                            atomic_add(&s_y[row * C + c], a * xj);
+                        }
+                    }
+                }
+            }
+            cur = nxt;
+        }
+        for (int e = p0; e < p1; ++e) {
+            const int pa = P.iv_row[e], L = P.iv_len[e];
+            const int qa = ia[pa], qe = ia[pa + L], qbase = qa & ~1;
+            __syncthreads();
+            for (int i = tid; i < L * C; i += B) {
+                const int ii = i / C, c = i % C;
+                s_xp[i] = c < nc ? (A)X[(int64_t)(pa + ii) * ldx + cc + c] : A(0);
+            }
+            fill_row_ids(ia, pa, pa + L, qbase, s_rid);
+            __syncthreads();
+            for (int qb = qbase + 2 * tid; qb < qe; qb += 2 * half) {
+#pragma unroll
+                for (int sp = 0; sp < 2; ++sp) {
+                    const int q = qb + half * sp;
+                    if (q >= qe) continue;
+                    int jj[2];
+                    pair<false>(ja, q, kend, jj);
+                    const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - qbase));
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int row = (int)((rv >> (16 * h)) & 0xFFFF);
+                        const int j = jj[h];
+                        if (row == (int)kNoRow || j < r0 || j >= r1) continue;
+                        const A u = (A)ldv(au, q + h);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) atomic_add(&s_y[(j - r0) * C + c], u * s_xp[row * C + c]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < T * C; e += B) {
+            const int i = e / C, c = e % C;
+            if (c < nc) Y[(int64_t)(r0 + i) * ldy + cc + c] = (YT)s_y[e];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ COLOR
 
 // One colour class [c0, c1) of the row list: write sets of its rows are
@@ -548,8 +808,8 @@ __global__ __launch_bounds__(512) void k_color(const int32_t *__restrict__ crow,
                                                const typename VT::V *__restrict__ ad,
                                                const typename VT::V *__restrict__ al,
                                                const typename VT::V *__restrict__ au,
-                                               const typename VT::X *__restrict__ x,
-                                               YT *__restrict__ y)
+                                               const typename VT::X *__restrict__ x, int64_t ldx,
+                                               YT *__restrict__ y, int64_t ldy)
 {
     using A = typename VT::A;
     const int lg = threadIdx.x % G;
@@ -557,12 +817,12 @@ __global__ __launch_bounds__(512) void k_color(const int32_t *__restrict__ crow,
     const int ngrp = gridDim.x * (blockDim.x / G);
     rows_loop<G, typename VT::V, A>(
         c0, c1, grp, ngrp, lg, [&](int idx) { return crow[idx]; }, [&](int r) { return ia[r]; },
-        [&](int r) { return (A)x[r]; }, [&](int r) { return (A)ldv(ad, r); }, ja, al, au,
+        [&](int r) { return (A)x[r * ldx]; }, [&](int r) { return (A)ldv(ad, r); }, ja, al, au,
         [&](int j, A a, A w) -> A {
-            y[j] = y[j] + (YT)w;
-            return a * (A)x[j];
+            y[j * ldy] = y[j * ldy] + (YT)w;
+            return a * (A)x[j * ldx];
         },
-        [&](int r, A v) { y[r] = y[r] + (YT)v; });
+        [&](int r, A v) { y[r * ldy] = y[r * ldy] + (YT)v; });
 }
 
 // --------------------------------------------------------------- dispatch
@@ -591,7 +851,7 @@ static int fill_grid(int64_t count) { return (int)std::min<int64_t>(4096, std::m
 
 template <class VT, class YT, int G>
 static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *al_, const void *au_,
-                          const void *x_, void *y_, void *ws, hipStream_t s)
+                          const void *x_, int64_t ldx, void *y_, int64_t ldy, int r, void *ws, hipStream_t s)
 {
     using V = typename VT::V;
     using X = typename VT::X;
@@ -603,60 +863,89 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
     const X *x = static_cast<const X *>(x_);
     YT *y = static_cast<YT *>(y_);
     const int B = p->o.block;
+    const bool single = r == 1 && ldx == 1 && ldy == 1;
     PlanDev P = plan_dev(p, ws);
+    auto set_lds = [](const void *kern, size_t lds) {
+        return lds > 65536 ? hip_status(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
+                           : (int)CSRC_OK;
+    };
     switch (p->o.variant) {
     case CSRC_V_PLAIN:
-        k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
-        k_plain<VT, YT><<<(n + 255) / 256, 256, 0, s>>>(n, A->ia, A->ja, ad, al, au, x, y);
+        k_fill_zero<YT><<<fill_grid((int64_t)n * r), 256, 0, s>>>(y, n, r, ldy);
+        for (int c = 0; c < r; ++c)
+            k_plain<VT, YT><<<(n + 255) / 256, 256, 0, s>>>(n, A->ia, A->ja, ad, al, au, x + c, ldx, y + c, ldy);
         break;
     case CSRC_V_ATOMIC: {
-        k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
+        k_fill_zero<YT><<<fill_grid((int64_t)n * r), 256, 0, s>>>(y, n, r, ldy);
         const int tmax = p->max_tile_rows;
         const size_t lds = (size_t)lds_atomic(tmax, p->max_tile_entries, sizeof(Acc));
         auto kern = k_atomic<VT, YT>;
-        if (lds > 65536 &&
-            hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
-            return CSRC_ERR_HIP;
-        kern<<<p->ntiles, B, lds, s>>>(P.tiles, P.tile_k, A->k, A->ia, A->ja, ad, al, au, x, y, tmax);
+        if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+        for (int c = 0; c < r; ++c)
+            kern<<<p->ntiles, B, lds, s>>>(P.tiles, P.tile_k, A->k, A->ia, A->ja, ad, al, au, x + c, ldx, y + c,
+                                           ldy, tmax);
         break;
     }
     case CSRC_V_PRIVATE: {
         const int tmax = p->max_tile_rows, wmax = p->max_window, emax = p->max_tile_entries;
-        const size_t lds = (size_t)lds_private(tmax, wmax, emax, p->max_intervals, sizeof(Acc));
-        auto kern = k_private<VT, YT>;
-        if (lds > 65536 &&
-            hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
-            return CSRC_ERR_HIP;
-        kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, emax);
-        if (p->nmerge_blocks > 0 && p->window_slots > 0) {
-            if (std::is_same<YT, double>::value)
-                k_merge<Acc, YT, double, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
-            else if (p->o.compensated)
-                k_merge<Acc, YT, float, true><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
-            else
-                k_merge<Acc, YT, float, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
+        if (single) {
+            const size_t lds = (size_t)lds_private(tmax, wmax, emax, p->max_intervals, sizeof(Acc));
+            auto kern = k_private<VT, YT>;
+            if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, emax);
+            if (p->nmerge_blocks > 0 && p->window_slots > 0) {
+                if (std::is_same<YT, double>::value)
+                    k_merge<Acc, YT, double, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
+                else if (p->o.compensated)
+                    k_merge<Acc, YT, float, true><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
+                else
+                    k_merge<Acc, YT, float, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
+            }
+        } else {
+            const size_t lds = (size_t)lds_private_mm(tmax, wmax, emax, p->max_intervals, sizeof(Acc),
+                                                      MmCols<VT>::C);
+            if (lds > (size_t)kLdsBudget) return CSRC_ERR_UNSUPPORTED;
+            auto kern = k_private_mm<VT, YT>;
+            if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, ldx, y, ldy, r, tmax, wmax, emax);
+            if (p->nmerge_blocks > 0 && p->window_slots > 0) {
+                if (std::is_same<YT, double>::value)
+                    k_merge_mm<Acc, YT, double, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y, ldy, r);
+                else if (p->o.compensated)
+                    k_merge_mm<Acc, YT, float, true><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y, ldy, r);
+                else
+                    k_merge_mm<Acc, YT, float, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y, ldy, r);
+            }
         }
         break;
     }
     case CSRC_V_OWNER: {
         const int tmax = p->max_tile_rows, pmax = p->max_pull_rows;
         const int emax = std::max(p->max_tile_entries, p->max_pull_entries);
-        const size_t lds = (size_t)lds_owner(tmax, pmax, emax, sizeof(Acc));
-        auto kern = k_owner<VT, YT>;
-        if (lds > 65536 &&
-            hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)))
-            return CSRC_ERR_HIP;
-        kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, pmax, emax);
+        if (single) {
+            const size_t lds = (size_t)lds_owner(tmax, pmax, emax, sizeof(Acc));
+            auto kern = k_owner<VT, YT>;
+            if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, pmax, emax);
+        } else {
+            const size_t lds = (size_t)lds_owner_mm(tmax, pmax, emax, sizeof(Acc), MmCols<VT>::C);
+            if (lds > (size_t)kLdsBudget) return CSRC_ERR_UNSUPPORTED;
+            auto kern = k_owner_mm<VT, YT>;
+            if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, ldx, y, ldy, r, tmax, pmax, emax);
+        }
         break;
     }
     case CSRC_V_COLOR: {
-        k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
-        for (int c = 0; c < p->ncolors; ++c) {
-            int c0 = p->cptr[c], c1 = p->cptr[c + 1];
-            int rows_per_block = (B / G) * kUnroll;
-            int grid = std::max(1, std::min(65535, (c1 - c0 + rows_per_block - 1) / rows_per_block));
-            k_color<G, VT, YT><<<grid, B, 0, s>>>(P.crow, c0, c1, A->ia, A->ja, ad, al, au, x, y);
-        }
+        k_fill_zero<YT><<<fill_grid((int64_t)n * r), 256, 0, s>>>(y, n, r, ldy);
+        for (int c = 0; c < r; ++c)
+            for (int cl = 0; cl < p->ncolors; ++cl) {
+                const int c0 = p->cptr[cl], c1 = p->cptr[cl + 1];
+                const int rows_per_block = (B / G) * kUnroll;
+                const int grid = std::max(1, std::min(65535, (c1 - c0 + rows_per_block - 1) / rows_per_block));
+                k_color<G, VT, YT><<<grid, B, 0, s>>>(P.crow, c0, c1, A->ia, A->ja, ad, al, au, x + c, ldx, y + c,
+                                                      ldy);
+            }
         break;
     }
     default:
@@ -667,15 +956,15 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
 
 template <class VT, class YT>
 static int launch_lanes(const csrc_plan *p, const csrc_matrix *A, const void *al, const void *au,
-                        const void *x, void *y, void *ws, hipStream_t s)
+                        const void *x, int64_t ldx, void *y, int64_t ldy, int r, void *ws, hipStream_t s)
 {
     switch (p->o.lanes) {
-    case 2: return launch_variant<VT, YT, 2>(p, A, al, au, x, y, ws, s);
-    case 4: return launch_variant<VT, YT, 4>(p, A, al, au, x, y, ws, s);
-    case 8: return launch_variant<VT, YT, 8>(p, A, al, au, x, y, ws, s);
-    case 16: return launch_variant<VT, YT, 16>(p, A, al, au, x, y, ws, s);
-    case 32: return launch_variant<VT, YT, 32>(p, A, al, au, x, y, ws, s);
-    case 64: return launch_variant<VT, YT, 64>(p, A, al, au, x, y, ws, s);
+    case 2: return launch_variant<VT, YT, 2>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
+    case 4: return launch_variant<VT, YT, 4>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
+    case 8: return launch_variant<VT, YT, 8>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
+    case 16: return launch_variant<VT, YT, 16>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
+    case 32: return launch_variant<VT, YT, 32>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
+    case 64: return launch_variant<VT, YT, 64>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
     default: return CSRC_ERR_PLAN;
     }
 }
@@ -702,26 +991,29 @@ int check_call(const csrc_matrix *A, const csrc_plan *p, void *ws, int64_t ws_by
     return CSRC_OK;
 }
 
-static int product(const csrc_matrix *A, const csrc_plan *p, const void *x, void *y, void *ws,
-                   int64_t ws_bytes, void *stream, bool transpose)
+static int product(const csrc_matrix *A, const csrc_plan *p, int32_t r, const void *x, int64_t ldx,
+                   void *y, int64_t ldy, void *ws, int64_t ws_bytes, void *stream, bool transpose)
 {
     int st = check_call(A, p, ws, ws_bytes);
     if (st) return st;
+    if (r < 1 || r > kMaxRhs || r > p->o.max_rhs || ldx < r || ldy < r) return CSRC_ERR_ARG;
     if (A->n == 0) return CSRC_OK;
     if (!x || !y) return CSRC_ERR_ARG;
-    int ys = (A->vdtype == CSRC_F64 || p->o.ydtype == CSRC_F64) ? 8 : 4;
-    if (overlap(x, (int64_t)A->n * xbytes(A->vdtype), y, (int64_t)A->n * ys)) return CSRC_ERR_ALIAS;
+    const int ys = (A->vdtype == CSRC_F64 || p->o.ydtype == CSRC_F64) ? 8 : 4;
+    const int64_t xspan = ((int64_t)(A->n - 1) * ldx + r) * xbytes(A->vdtype);
+    const int64_t yspan = ((int64_t)(A->n - 1) * ldy + r) * ys;
+    if (overlap(x, xspan, y, yspan)) return CSRC_ERR_ALIAS;
     const void *al = transpose ? A->au : A->al;
     const void *au = transpose ? A->al : A->au;
     hipStream_t s = static_cast<hipStream_t>(stream);
     switch (A->vdtype) {
-    case CSRC_F64: return launch_lanes<F64T, double>(p, A, al, au, x, y, ws, s);
+    case CSRC_F64: return launch_lanes<F64T, double>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
     case CSRC_F32:
-        return p->o.ydtype == CSRC_F64 ? launch_lanes<F32T, double>(p, A, al, au, x, y, ws, s)
-                                       : launch_lanes<F32T, float>(p, A, al, au, x, y, ws, s);
+        return p->o.ydtype == CSRC_F64 ? launch_lanes<F32T, double>(p, A, al, au, x, ldx, y, ldy, r, ws, s)
+                                       : launch_lanes<F32T, float>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
     case CSRC_BF16:
-        return p->o.ydtype == CSRC_F64 ? launch_lanes<B16T, double>(p, A, al, au, x, y, ws, s)
-                                       : launch_lanes<B16T, float>(p, A, al, au, x, y, ws, s);
+        return p->o.ydtype == CSRC_F64 ? launch_lanes<B16T, double>(p, A, al, au, x, ldx, y, ldy, r, ws, s)
+                                       : launch_lanes<B16T, float>(p, A, al, au, x, ldx, y, ldy, r, ws, s);
     default: return CSRC_ERR_ARG;
     }
 }
@@ -731,11 +1023,23 @@ static int product(const csrc_matrix *A, const csrc_plan *p, const void *x, void
 extern "C" int csrc_spmv(const csrc_matrix *A, const csrc_plan *plan, const void *x, void *y,
                          void *workspace, int64_t ws_bytes, void *stream)
 {
-    return csrc::product(A, plan, x, y, workspace, ws_bytes, stream, false);
+    return csrc::product(A, plan, 1, x, 1, y, 1, workspace, ws_bytes, stream, false);
 }
 
 extern "C" int csrc_spmv_t(const csrc_matrix *A, const csrc_plan *plan, const void *x, void *y,
                            void *workspace, int64_t ws_bytes, void *stream)
 {
-    return csrc::product(A, plan, x, y, workspace, ws_bytes, stream, true);
+    return csrc::product(A, plan, 1, x, 1, y, 1, workspace, ws_bytes, stream, true);
+}
+
+extern "C" int csrc_spmm(const csrc_matrix *A, const csrc_plan *plan, int32_t r, const void *X, int64_t ldx,
+                         void *Y, int64_t ldy, void *workspace, int64_t ws_bytes, void *stream)
+{
+    return csrc::product(A, plan, r, X, ldx, Y, ldy, workspace, ws_bytes, stream, false);
+}
+
+extern "C" int csrc_spmm_t(const csrc_matrix *A, const csrc_plan *plan, int32_t r, const void *X, int64_t ldx,
+                           void *Y, int64_t ldy, void *workspace, int64_t ws_bytes, void *stream)
+{
+    return csrc::product(A, plan, r, X, ldx, Y, ldy, workspace, ws_bytes, stream, true);
 }

@@ -43,6 +43,16 @@ inline int64_t lds_atomic(int64_t tmax, int64_t emax, int acc)
 {
     return align16(2 * tmax * acc) + align16((emax + 4) * 2);
 }
+// multi-column forms: C columns of each per-row and per-slot array
+inline int64_t lds_private_mm(int64_t tmax, int64_t wmax, int64_t emax, int64_t ivmax, int acc, int C)
+{
+    return align16((2 * tmax + 2 * wmax) * C * acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+}
+inline int64_t lds_owner_mm(int64_t tmax, int64_t pmax, int64_t emax, int acc, int C)
+{
+    return align16((2 * tmax + pmax) * C * acc) + align16((emax + 4) * 2);
+}
+inline int mm_columns(int32_t vdtype) { return vdtype == CSRC_F64 ? 4 : 8; }
 
 // A table placed in the device workspace.
 struct Table {

@@ -1,0 +1,74 @@
+"""Reduced-precision storage (FP32 / BF16 values, FP32 x, FP32 accumulation),
+every variant, y in FP32 or FP64, with and without the compensated merge.
+
+Bars (Higham's bound for sums of m rounded products in any order):
+* against the FP64 oracle on the stored (dequantised) values and rounded x:
+  |y_hat - y~| <= gamma_m(2^-24) (|A~| |x~|)_i            (accumulation only)
+* against the FP64 oracle on the original FP64 data: the stated total bound
+  (u_v + u_x + gamma_m(2^-24)(1+u_v)(1+u_x)) (|A| |x|)_i, u_v = 2^-24 or 2^-8
+* integer-valued data: bit-exact (every sum is an integer below 2^24).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import reference as R
+from synth import workloads as W
+from tests.helpers import oracle_csrc, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["plain", "atomic", "private", "color", "owner"]
+
+
+def run(C, torch, host, x, variant, dtype, ydtype, transpose=False, **kw):
+    A = C.Matrix(host, dtype)
+    plan = C.Plan(A, variant, ydtype=ydtype, **kw)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32)
+    y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+    (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("ydtype", ["f32", "f64"])
+def test_reduced_precision_bounds(variant, dtype, ydtype):
+    import torch
+    import paper_1003_0952_amd as C
+    a, x = W.tet_mesh(8)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    ov = {s: R.dequantize(c[s], dtype) for s in ("ad", "al", "au")}
+    xf = R.to_f32(x).astype(np.float64)
+    uv = R.UNIT_ROUNDOFF[dtype]
+    m = R.row_terms(c)
+    for transpose in (False, True):
+        for comp in (False, True):
+            y = run(C, torch, host, x, variant, dtype, ydtype, transpose, compensated=comp)
+            f = R.spmv_t if transpose else R.spmv
+            ref_stored = f(c, xf, **ov)
+            acc_bound = R.accumulation_bound(c, xf, 2.0**-24, transpose, **ov)
+            if ydtype == "f32":
+                acc_bound = acc_bound + 2.0**-24 * np.abs(ref_stored)
+            assert np.all(np.abs(y - ref_stored) <= acc_bound), (variant, dtype, transpose)
+            ref64 = f(c, x)
+            scale = R.abs_product(c, x, transpose)
+            total = (uv + 2.0**-24 + R.gamma(m + 1, 2.0**-24) * (1 + uv) * (1 + 2.0**-24)) * scale
+            assert np.all(np.abs(y - ref64) <= total)
+            print(f"{variant} {dtype} y={ydtype} T={transpose} comp={comp}: rel_inf vs stored "
+                  f"{rel_inf(y, ref_stored):.2e}, vs fp64 {rel_inf(y, ref64):.2e}")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_reduced_precision_integer_exact(variant, dtype):
+    import torch
+    import paper_1003_0952_amd as C
+    a, x = W.hex_mesh(11, "random", kind="int")
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    for transpose in (False, True):
+        y = run(C, torch, host, x, variant, dtype, "f32", transpose)
+        assert np.array_equal(y, (R.spmv_t if transpose else R.spmv)(c, x))
