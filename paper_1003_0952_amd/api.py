@@ -217,3 +217,99 @@ def spmv(A, plan, x, y=None, transpose=False, stream=None):
     if y is None:
         y = torch.empty(A.n, dtype=plan.ytorch, device=x.device)
     return (csrc_spmv_t if transpose else csrc_spmv)(A, plan, x, y, stream)
+
+
+# ------------------------------------------------------------------ batches
+
+class BatchPlan:
+    """Plan of many independent products run in one persistent launch.
+
+    ``mats`` are Matrix objects of one storage type, ``rs`` their numbers of
+    right-hand sides (1..32).  The workspace lives as long as the plan.
+    """
+
+    def __init__(self, mats, rs, tile_work=0, block=0, grid=0, ydtype="f32"):
+        import torch
+        self.mats = list(mats)
+        self.rs = [int(r) for r in rs]
+        m = len(self.mats)
+        vd = self.mats[0].vdtype if m else B.F64
+        n = np.array([a.n for a in self.mats], dtype=np.int32)
+        self._ia = [a.host_ia for a in self.mats]
+        self._ja = [a.host_ja for a in self.mats]
+        ia_p = (ctypes.c_void_p * max(m, 1))(*[np_ptr(x).value for x in self._ia])
+        ja_p = (ctypes.c_void_p * max(m, 1))(*[np_ptr(x).value for x in self._ja])
+        r = np.array(self.rs, dtype=np.int32)
+        opts = B.BatchOpts(int(tile_work), int(block), int(grid), _dt(ydtype))
+        h = ctypes.c_void_p(0)
+        check(B.lib.csrc_batch_plan_create(m, np_ptr(n), ia_p, ja_p, np_ptr(r), vd, ctypes.byref(opts),
+                                           ctypes.byref(h)), "csrc_batch_plan_create")
+        self._h = h
+        self.vdtype = vd
+        self.ydtype = B.F64 if vd == B.F64 else _dt(ydtype)
+        self.ws_bytes = int(B.lib.csrc_batch_workspace_bytes(h))
+        dev = self.mats[0].device if m else "cuda"
+        self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self._graphs = []
+
+    def __del__(self):
+        for g in getattr(self, "_graphs", []):
+            if B is not None and getattr(B, "lib", None) is not None:
+                B.lib.csrc_graph_destroy(g)
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and B is not None and getattr(B, "lib", None) is not None:
+            B.lib.csrc_batch_plan_destroy(h)
+            self._h = None
+
+    @property
+    def ytorch(self):
+        import torch
+        return torch.float64 if self.ydtype == B.F64 else torch.float32
+
+    def _arrays(self, Xs, Ys):
+        m = len(self.mats)
+        descs = (B.CsrcMatrix * max(m, 1))(*[a.desc for a in self.mats])
+        xp = (ctypes.c_void_p * max(m, 1))(*[t_ptr(x).value for x in Xs])
+        yp = (ctypes.c_void_p * max(m, 1))(*[t_ptr(y).value for y in Ys])
+        ldx = np.array([x.stride(0) for x in Xs], dtype=np.int64)
+        ldy = np.array([y.stride(0) for y in Ys], dtype=np.int64)
+        return descs, xp, ldx, yp, ldy
+
+    def bind(self, Xs, Ys, stream=None):
+        """Upload tables and the per-matrix pointers (X[m], Y[m]: n x r 2-D tensors)."""
+        self._bound = (list(Xs), list(Ys))
+        descs, xp, ldx, yp, ldy = self._arrays(Xs, Ys)
+        check(B.lib.csrc_batch_bind(self._h, descs, xp, np_ptr(ldx), yp, np_ptr(ldy), t_ptr(self.workspace),
+                                    self.ws_bytes, stream_ptr(stream)), "csrc_batch_bind")
+
+    def run(self, transpose=False, stream=None):
+        check(B.lib.csrc_batch_run(self._h, 1 if transpose else 0, t_ptr(self.workspace), self.ws_bytes,
+                                   stream_ptr(stream)), "csrc_batch_run")
+
+    def graph(self, transpose=False):
+        """An instantiated HIP graph of the bound launch; call launch_graph(g)."""
+        g = ctypes.c_void_p(0)
+        check(B.lib.csrc_batch_graph_create(self._h, 1 if transpose else 0, t_ptr(self.workspace),
+                                            self.ws_bytes, ctypes.byref(g)), "csrc_batch_graph_create")
+        self._graphs.append(g)
+        return g
+
+    @staticmethod
+    def launch_graph(g, stream=None):
+        check(B.lib.csrc_graph_launch(g, stream_ptr(stream)), "csrc_graph_launch")
+
+
+def csrc_spmv_batched(bplan, Xs, Ys, stream=None):
+    """Bind then run Y[m] <- A[m] X[m] for every matrix of the batch plan."""
+    bplan._bound = (list(Xs), list(Ys))
+    descs, xp, ldx, yp, ldy = bplan._arrays(Xs, Ys)
+    check(B.lib.csrc_spmv_batched(bplan._h, descs, xp, np_ptr(ldx), yp, np_ptr(ldy), t_ptr(bplan.workspace),
+                                  bplan.ws_bytes, stream_ptr(stream)), "csrc_spmv_batched")
+
+
+def csrc_spmv_t_batched(bplan, Xs, Ys, stream=None):
+    """Bind then run Y[m] <- A[m]^T X[m] for every matrix of the batch plan."""
+    bplan._bound = (list(Xs), list(Ys))
+    descs, xp, ldx, yp, ldy = bplan._arrays(Xs, Ys)
+    check(B.lib.csrc_spmv_t_batched(bplan._h, descs, xp, np_ptr(ldx), yp, np_ptr(ldy), t_ptr(bplan.workspace),
+                                    bplan.ws_bytes, stream_ptr(stream)), "csrc_spmv_t_batched")

@@ -561,19 +561,20 @@ __device__ __forceinline__ void mm_entry(A a, A u, const A *xr, const A *xj, A *
     }
 }
 
+// One PRIVATE tile t of a product with r columns (r >= 1).  Used by the
+// multi-column kernel and by the batched persistent kernel.
 template <class VT, class YT>
-__global__ __launch_bounds__(512) void k_private_mm(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
-                                                    const int32_t *__restrict__ ja,
-                                                    const typename VT::V *__restrict__ ad,
-                                                    const typename VT::V *__restrict__ al,
-                                                    const typename VT::V *__restrict__ au,
-                                                    const typename VT::X *__restrict__ X, int64_t ldx,
-                                                    YT *__restrict__ Y, int64_t ldy, int r, int tmax,
-                                                    int wmax, int emax)
+__device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, int64_t kend,
+                                                const int32_t *__restrict__ ia, const int32_t *__restrict__ ja,
+                                                const typename VT::V *__restrict__ ad,
+                                                const typename VT::V *__restrict__ al,
+                                                const typename VT::V *__restrict__ au,
+                                                const typename VT::X *__restrict__ X, int64_t ldx,
+                                                YT *__restrict__ Y, int64_t ldy, int r, int tmax, int wmax,
+                                                int emax, unsigned char *lds)
 {
     using A = typename VT::A;
     constexpr int C = MmCols<VT>::C;
-    extern __shared__ __align__(16) unsigned char lds[];
     A *s_x = reinterpret_cast<A *>(lds);
     A *s_y = s_x + (int64_t)tmax * C;
     A *s_xw = s_y + (int64_t)tmax * C;
@@ -583,12 +584,12 @@ __global__ __launch_bounds__(512) void k_private_mm(PlanDev P, int64_t kend, con
     int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                                    align16(((int64_t)emax + 4) * 2));
     const int tid = threadIdx.x, B = blockDim.x;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
     const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
     const int e0 = P.iv_ptr[t], NI = P.iv_ptr[t + 1] - e0;
     int32_t *s_ivslot = s_ivrow + NI;
     const int W = NI ? P.iv_slot[e0 + NI - 1] + P.iv_len[e0 + NI - 1] : 0;
+    __syncthreads();   // the workgroup's previous use of LDS is finished
     for (int i = tid; i < NI; i += B) {
         s_ivrow[i] = P.iv_row[e0 + i];
         s_ivslot[i] = P.iv_slot[e0 + i];
@@ -659,13 +660,27 @@ __global__ __launch_bounds__(512) void k_private_mm(PlanDev P, int64_t kend, con
     }
 }
 
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_private_mm(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
+                                                    const int32_t *__restrict__ ja,
+                                                    const typename VT::V *__restrict__ ad,
+                                                    const typename VT::V *__restrict__ al,
+                                                    const typename VT::V *__restrict__ au,
+                                                    const typename VT::X *__restrict__ X, int64_t ldx,
+                                                    YT *__restrict__ Y, int64_t ldy, int r, int tmax,
+                                                    int wmax, int emax)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    private_tile_mm<VT, YT>(P, xcd_tile(blockIdx.x, gridDim.x), kend, ia, ja, ad, al, au, X, ldx, Y, ldy, r,
+                            tmax, wmax, emax, lds);
+}
+
 // Merge pass for r columns: Y[i, c] += partial slots covering row i, in
 // ascending tile order; partial slot g of a tile holds r values.
 template <class A, class YT, class MT, bool COMP>
-__global__ __launch_bounds__(kMergeBlock) void k_merge_mm(int32_t n, PlanDev P, YT *__restrict__ Y,
-                                                          int64_t ldy, int r)
+__device__ __forceinline__ void merge_block_mm(int32_t n, const PlanDev &P, YT *__restrict__ Y, int64_t ldy,
+                                               int r, int b)
 {
-    const int b = blockIdx.x;
     const int e0 = P.mb_ptr[b], e1 = P.mb_ptr[b + 1];
     if (e0 == e1) return;
     const A *part = reinterpret_cast<const A *>(P.partials);
@@ -689,6 +704,50 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_mm(int32_t n, PlanDev P, 
             }
         }
         Y[(int64_t)i * ldy + c] = (YT)(s + cm);
+    }
+}
+
+template <class A, class YT, class MT, bool COMP>
+__global__ __launch_bounds__(kMergeBlock) void k_merge_mm(int32_t n, PlanDev P, YT *__restrict__ Y,
+                                                          int64_t ldy, int r)
+{
+    merge_block_mm<A, YT, MT, COMP>(n, P, Y, ldy, r, blockIdx.x);
+}
+
+// ----------------------------------------------------------------- batched
+//
+// Many independent products in one persistent launch: the work list holds
+// (matrix, tile) items sorted by decreasing cost, and each workgroup walks it
+// with a grid stride; a second launch merges the window partials of every
+// matrix (work list of (matrix, merge block)).  Both launches read only the
+// bound workspace, so they can be recorded into a HIP graph.
+
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_batch_tiles(const MatDev *__restrict__ mats, const int2 *__restrict__ items,
+                                                     int nitems, int transpose, int tmax, int wmax, int emax)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    using V = typename VT::V;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 w = items[it];
+        const MatDev &M = mats[w.x];
+        const V *al = static_cast<const V *>(transpose ? M.au : M.al);
+        const V *au = static_cast<const V *>(transpose ? M.al : M.au);
+        private_tile_mm<VT, YT>(M.P, w.y, M.k, M.ia, M.ja, static_cast<const V *>(M.ad), al, au,
+                                static_cast<const typename VT::X *>(M.X), M.ldx, static_cast<YT *>(M.Y), M.ldy,
+                                M.r, tmax, wmax, emax, lds);
+    }
+}
+
+template <class A, class YT, class MT, bool COMP>
+__global__ __launch_bounds__(kMergeBlock) void k_batch_merge(const MatDev *__restrict__ mats,
+                                                             const int2 *__restrict__ items, int nitems)
+{
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 w = items[it];
+        const MatDev &M = mats[w.x];
+        merge_block_mm<A, YT, MT, COMP>(M.n, M.P, static_cast<YT *>(M.Y), M.ldy, M.r, w.y);
+        __syncthreads();
     }
 }
 
@@ -826,6 +885,25 @@ __global__ __launch_bounds__(512) void k_color(const int32_t *__restrict__ crow,
 }
 
 // --------------------------------------------------------------- dispatch
+
+PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials)
+{
+    auto at = [&](const Table &t) -> const void * { return base ? base + t.offset : nullptr; };
+    PlanDev d;
+    d.tiles = (const int32_t *)at(p->t_tiles);
+    d.tile_k = (const int32_t *)at(p->t_tile_k);
+    d.iv_ptr = (const int32_t *)at(p->t_iv_ptr);
+    d.iv_row = (const int32_t *)at(p->t_iv_row);
+    d.iv_len = (const int32_t *)at(p->t_iv_len);
+    d.iv_slot = (const int32_t *)at(p->t_iv_slot);
+    d.iv_goff = (const int64_t *)at(p->t_iv_goff);
+    d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
+    d.mb_iv = (const int32_t *)at(p->t_mb_iv);
+    d.crow = (const int32_t *)at(p->t_crow);
+    d.cptr = nullptr;
+    d.partials = partials;
+    return d;
+}
 
 static PlanDev plan_dev(const csrc_plan *p, void *ws)
 {
@@ -1042,4 +1120,174 @@ extern "C" int csrc_spmm_t(const csrc_matrix *A, const csrc_plan *plan, int32_t 
                            void *Y, int64_t ldy, void *workspace, int64_t ws_bytes, void *stream)
 {
     return csrc::product(A, plan, r, X, ldx, Y, ldy, workspace, ws_bytes, stream, true);
+}
+
+// ------------------------------------------------------------ batch launches
+
+namespace csrc {
+
+struct BatchLaunch {
+    const void *tiles_fn = nullptr;
+    const void *merge_fn = nullptr;
+    int grid = 0, merge_grid = 0, block = 512;
+    size_t lds = 0;
+};
+
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+template <class VT, class YT>
+static void batch_fns(BatchLaunch &L)
+{
+    using Acc = typename VT::A;
+    L.tiles_fn = (const void *)k_batch_tiles<VT, YT>;
+    if (std::is_same<YT, double>::value)
+        L.merge_fn = (const void *)k_batch_merge<Acc, YT, double, false>;
+    else
+        L.merge_fn = (const void *)k_batch_merge<Acc, YT, float, false>;
+}
+
+static int batch_launch_config(const csrc_batch_plan *b, BatchLaunch &L)
+{
+    switch (b->vdtype) {
+    case CSRC_F64: batch_fns<F64T, double>(L); break;
+    case CSRC_F32:
+        if (b->ydtype == CSRC_F64) batch_fns<F32T, double>(L); else batch_fns<F32T, float>(L);
+        break;
+    default:
+        if (b->ydtype == CSRC_F64) batch_fns<B16T, double>(L); else batch_fns<B16T, float>(L);
+    }
+    L.block = b->o.block;
+    L.lds = (size_t)b->lds;
+    const int cus = device_cus();
+    const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, kLdsBudget / std::max<int64_t>(1, b->lds)));
+    const int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
+    L.grid = b->o.grid > 0 ? b->o.grid : std::max(1, std::min(nitems, cus * per_cu));
+    L.merge_grid = std::max(1, std::min(nm, cus * 8));
+    if (L.lds > 65536)
+        return hip_status(hipFuncSetAttribute(L.tiles_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
+    return CSRC_OK;
+}
+
+}  // namespace csrc
+
+extern "C" int csrc_batch_run(const csrc_batch_plan *b, int32_t transpose, void *workspace, int64_t ws_bytes,
+                              void *stream)
+{
+    using namespace csrc;
+    if (!b) return CSRC_ERR_ARG;
+    if (!workspace || ws_bytes < b->ws_bytes) return CSRC_ERR_WORKSPACE;
+    const int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
+    if (nitems == 0) return CSRC_OK;
+    BatchLaunch L;
+    int st = batch_launch_config(b, L);
+    if (st) return st;
+    char *ws = static_cast<char *>(workspace);
+    const MatDev *mats = reinterpret_cast<const MatDev *>(ws + b->off_descs);
+    const int2 *items = reinterpret_cast<const int2 *>(ws + b->off_items);
+    const int2 *mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
+    int tr = transpose ? 1 : 0, tmax = b->tmax, wmax = b->wmax, emax = b->emax;
+    void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&tmax, (void *)&wmax,
+                     (void *)&emax};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = hip_status(hipLaunchKernel(L.tiles_fn, dim3(L.grid), dim3(L.block), args1, L.lds, s));
+    if (st || nm == 0) return st;
+    void *args2[] = {(void *)&mats, (void *)&mitems, (void *)&nm};
+    return hip_status(hipLaunchKernel(L.merge_fn, dim3(L.merge_grid), dim3(kMergeBlock), args2, 0, s));
+}
+
+extern "C" int csrc_spmv_batched(const csrc_batch_plan *b, const csrc_matrix *A, const void *const *X,
+                                 const int64_t *ldx, void *const *Y, const int64_t *ldy, void *workspace,
+                                 int64_t ws_bytes, void *stream)
+{
+    int st = csrc_batch_bind(b, A, X, ldx, Y, ldy, workspace, ws_bytes, stream);
+    return st ? st : csrc_batch_run(b, 0, workspace, ws_bytes, stream);
+}
+
+extern "C" int csrc_spmv_t_batched(const csrc_batch_plan *b, const csrc_matrix *A, const void *const *X,
+                                   const int64_t *ldx, void *const *Y, const int64_t *ldy, void *workspace,
+                                   int64_t ws_bytes, void *stream)
+{
+    int st = csrc_batch_bind(b, A, X, ldx, Y, ldy, workspace, ws_bytes, stream);
+    return st ? st : csrc_batch_run(b, 1, workspace, ws_bytes, stream);
+}
+
+extern "C" int csrc_batch_graph_create(const csrc_batch_plan *b, int32_t transpose, void *workspace,
+                                       int64_t ws_bytes, csrc_graph **out)
+{
+    using namespace csrc;
+    if (!b || !out) return CSRC_ERR_ARG;
+    if (!workspace || ws_bytes < b->ws_bytes) return CSRC_ERR_WORKSPACE;
+    *out = nullptr;
+    BatchLaunch L;
+    int st = batch_launch_config(b, L);
+    if (st) return st;
+    char *ws = static_cast<char *>(workspace);
+    const MatDev *mats = reinterpret_cast<const MatDev *>(ws + b->off_descs);
+    const int2 *items = reinterpret_cast<const int2 *>(ws + b->off_items);
+    const int2 *mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
+    int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
+    int tr = transpose ? 1 : 0, tmax = b->tmax, wmax = b->wmax, emax = b->emax;
+    hipGraph_t g = nullptr;
+    st = hip_status(hipGraphCreate(&g, 0));
+    if (st) return st;
+    hipGraphNode_t n1 = nullptr, n2 = nullptr;
+    if (nitems > 0) {
+        void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&tmax,
+                         (void *)&wmax, (void *)&emax};
+        hipKernelNodeParams k1{};
+        k1.func = const_cast<void *>(L.tiles_fn);
+        k1.gridDim = dim3(L.grid);
+        k1.blockDim = dim3(L.block);
+        k1.sharedMemBytes = (unsigned)L.lds;
+        k1.kernelParams = args1;
+        st = hip_status(hipGraphAddKernelNode(&n1, g, nullptr, 0, &k1));
+        if (!st && nm > 0) {
+            void *args2[] = {(void *)&mats, (void *)&mitems, (void *)&nm};
+            hipKernelNodeParams k2{};
+            k2.func = const_cast<void *>(L.merge_fn);
+            k2.gridDim = dim3(L.merge_grid);
+            k2.blockDim = dim3(kMergeBlock);
+            k2.sharedMemBytes = 0;
+            k2.kernelParams = args2;
+            st = hip_status(hipGraphAddKernelNode(&n2, g, &n1, 1, &k2));
+        }
+    }
+    hipGraphExec_t ex = nullptr;
+    if (!st) st = hip_status(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    if (st) {
+        hipGraphDestroy(g);
+        return st;
+    }
+    csrc_graph *cg = new (std::nothrow) csrc_graph();
+    if (!cg) {
+        hipGraphExecDestroy(ex);
+        hipGraphDestroy(g);
+        return CSRC_ERR_NOMEM;
+    }
+    cg->graph = g;
+    cg->exec = ex;
+    *out = cg;
+    return CSRC_OK;
+}
+
+extern "C" int csrc_graph_launch(csrc_graph *g, void *stream)
+{
+    if (!g || !g->exec) return CSRC_ERR_ARG;
+    return csrc::hip_status(hipGraphLaunch(static_cast<hipGraphExec_t>(g->exec), static_cast<hipStream_t>(stream)));
+}
+
+extern "C" int csrc_graph_destroy(csrc_graph *g)
+{
+    if (!g) return CSRC_OK;
+    if (g->exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(g->exec));
+    if (g->graph) (void)hipGraphDestroy(static_cast<hipGraph_t>(g->graph));
+    delete g;
+    return CSRC_OK;
 }

@@ -76,7 +76,23 @@ struct PlanDev {
     void *partials;            // partial buffer (PRIVATE)
 };
 
-struct csrc_plan_impl;
+// One bound matrix of a batch (written into the workspace by
+// csrc_batch_bind): its arrays, blocks and plan tables.
+struct MatDev {
+    PlanDev P;
+    int64_t k;
+    const int32_t *ia;
+    const int32_t *ja;
+    const void *ad;
+    const void *al;
+    const void *au;
+    const void *X;
+    int64_t ldx;
+    void *Y;
+    int64_t ldy;
+    int32_t n;
+    int32_t r;
+};
 
 }  // namespace csrc
 
@@ -117,3 +133,31 @@ int hip_status(int hip_error);
 int color_rows(int32_t n, const int32_t *ia, const int32_t *ja, int32_t criterion,
                int32_t *color, int32_t *ncolors);
 }
+
+// A batch of independent products: one PRIVATE plan per matrix, their tables
+// concatenated into one workspace image with the work lists.
+struct csrc_batch_plan {
+    int32_t nmat = 0;
+    int32_t vdtype = CSRC_F64;
+    int32_t ydtype = CSRC_F64;
+    csrc_batch_opts o{};
+    std::vector<csrc_plan *> plans;
+    std::vector<int32_t> n, r;
+    std::vector<int64_t> blob_off;   // table image of matrix m in the workspace
+    std::vector<int64_t> part_off;   // partial slots of matrix m (bytes, from off_parts)
+    std::vector<int32_t> items;      // (matrix, tile) pairs, decreasing cost
+    std::vector<int32_t> mitems;     // (matrix, merge block) pairs
+    int32_t tmax = 0, wmax = 0, emax = 0, ivmax = 0;
+    int64_t lds = 0;
+    std::vector<char> blob;          // tables + work lists (uploaded by bind)
+    int64_t off_items = 0, off_mitems = 0, off_descs = 0, off_parts = 0, ws_bytes = 0;
+    ~csrc_batch_plan()
+    {
+        for (auto *p : plans) delete p;
+    }
+};
+
+struct csrc_graph {
+    void *graph = nullptr;   // hipGraph_t
+    void *exec = nullptr;    // hipGraphExec_t
+};
