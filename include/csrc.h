@@ -374,22 +374,25 @@ int64_t csrc_mlp_param_count(int32_t hidden, int32_t classes);
  * csrc_mlp_forward -- logits[B*K] and probabilities probs[B*K] for a batch
  * of B feature rows feats[B*12] (device).  act may be NULL; otherwise it
  * receives the hidden activations [B*2H] needed by csrc_mlp_backward.
+ * 1 <= hidden <= 256, 1 <= classes <= 64.  FP32, one workgroup per row.
  */
 int csrc_mlp_forward(int32_t hidden, int32_t classes, int32_t batch,
                      const float *params, const float *feats, float *act,
                      float *logits, float *probs, void *stream);
 
 /*
- * csrc_mlp_backward -- mean softmax cross-entropy loss over the batch for
- * integer labels[B] (device) and its gradient grads[param_count] (device,
- * overwritten).  loss (device, 1 float) may be NULL.  Needs the act and
- * probs written by csrc_mlp_forward on the same batch.
+ * csrc_mlp_backward -- gradient grads[param_count] (device, overwritten) of
+ * the mean softmax cross-entropy over the batch for integer labels[B]
+ * (device, in [0, K)), and the loss itself in loss[0] (device; may be NULL).
+ * Needs act and probs written by csrc_mlp_forward on the same batch and a
+ * device work buffer of B*(2H+K) floats.  Every sum over the batch runs in a
+ * fixed order, so equal inputs give bit-identical gradients.
  */
 int csrc_mlp_backward(int32_t hidden, int32_t classes, int32_t batch,
                       const float *params, const float *feats,
                       const float *act, const float *probs,
                       const int32_t *labels, float *grads, float *loss,
-                      void *stream);
+                      float *work, void *stream);
 
 /*
  * csrc_mlp_adam -- one Adam step (Kingma and Ba) on params with moment
@@ -398,6 +401,16 @@ int csrc_mlp_backward(int32_t hidden, int32_t classes, int32_t batch,
 int csrc_mlp_adam(int64_t count, float *params, const float *grads, float *m,
                   float *v, int32_t step, float lr, float beta1, float beta2,
                   float eps, void *stream);
+
+/*
+ * csrc_mlp_predict_host -- inference on the host: standardise the 12
+ * features as (f - mean) / scale, run the network (host memory, FP32) and
+ * return the arg-max class in *cls (ties to the lower index).  Used to pick
+ * a variant for a new matrix without any device work.
+ */
+int csrc_mlp_predict_host(int32_t hidden, int32_t classes, const float *params,
+                          const float *mean, const float *scale,
+                          const float *features, int32_t *cls);
 
 #ifdef __cplusplus
 }

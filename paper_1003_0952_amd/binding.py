@@ -135,7 +135,8 @@ _sig("csrc_color", ctypes.c_int, [I32, P, P, I32, P, P])
 _sig("csrc_features", ctypes.c_int, [I32, P, P, I32, I32, P])
 _sig("csrc_mlp_param_count", I64, [I32, I32])
 _sig("csrc_mlp_forward", ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P])
-_sig("csrc_mlp_backward", ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P])
+_sig("csrc_mlp_backward", ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P, P])
+_sig("csrc_mlp_predict_host", ctypes.c_int, [I32, I32, P, P, P, P, P])
 _sig("csrc_mlp_adam", ctypes.c_int, [I64, P, P, P, P, I32, F32, F32, F32, F32, P])
 
 lib = _lib
