@@ -17,7 +17,7 @@ from . import tuner
 
 HIDDEN = 64
 NF = B.NFEATURES
-MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_model.json")
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data", "model.json")
 
 
 def param_count(H, K):

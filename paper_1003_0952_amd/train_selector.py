@@ -1,0 +1,211 @@
+"""Build the learned selector: time every candidate on seeded matrices of the
+selector family, train the network on the GPU, evaluate on held-out matrices.
+
+  python -m paper_1003_0952_amd.train_selector campaign --count 2000 --db DB
+  python -m paper_1003_0952_amd.train_selector train --db DB
+
+The campaign is resumable (one JSON line per matrix; finished matrices are
+skipped) and stops after --budget seconds so it can run in several pieces.
+Matrices m >= --heldout-from are never trained on.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DATA = os.path.join(HERE, "selector_data")
+MALL = 256 * 2**20
+
+
+def _prepare(args):
+    """Worker: generate matrix m and its host CSRC arrays and features."""
+    m, nnz_cap = args
+    sys.path.insert(0, os.path.dirname(HERE))
+    from synth import workloads as W
+    from paper_1003_0952_amd import api as C
+    spec = W.family_spec(m, nnz_cap=nnz_cap)
+    a, x = W.family_member(spec)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    f = C.csrc_features(host["ia"], host["ja"], "f64", -1)
+    return m, spec, host, x, f
+
+
+def campaign(args):
+    done = set()
+    if os.path.exists(args.db):
+        with open(args.db) as fh:
+            for line in fh:
+                if line.strip():
+                    done.add(json.loads(line)["m"])
+    todo = [m for m in range(args.count) if m not in done]
+    print(f"# campaign: {len(done)} done, {len(todo)} to go", flush=True)
+    if not todo:
+        return
+    # fork the workers before this process touches the GPU
+    pool = ProcessPoolExecutor(max_workers=args.workers)
+    import torch
+    from paper_1003_0952_amd import api as C, tuner as T
+    t0 = time.time()
+    threads = ThreadPoolExecutor(max_workers=len(T.CANDIDATES))
+    from collections import deque
+    pending = deque()
+    queue = list(todo)
+
+    def refill():
+        # a bounded window of prepared matrices (each may be tens of MB)
+        while queue and len(pending) < 2 * args.workers:
+            pending.append(pool.submit(_prepare, (queue.pop(0), args.nnz_cap)))
+
+    def results():
+        refill()
+        while pending:
+            r = pending.popleft().result()
+            refill()
+            yield r
+
+    count = 0
+    with open(args.db, "a") as out:
+        for m, spec, host, x, f in results():
+            A = C.Matrix(host, "f64")
+            ncopy = 3 if A.nbytes() > MALL // 3 else 1
+            mats = [A] + [C.Matrix(host, "f64") for _ in range(ncopy - 1)]
+            xs = [torch.from_numpy(x).cuda() for _ in mats]
+            ys = [torch.empty(A.n, dtype=torch.float64, device="cuda") for _ in mats]
+
+            def mk(i):
+                v, kw = T.CANDIDATES[i]
+                try:
+                    return C.Plan(A, v, **kw)
+                except C.CsrcError:
+                    return None
+            plans = list(threads.map(mk, range(len(T.CANDIDATES))))
+            times = []
+            for p in plans:
+                if p is None:
+                    times.append(float("inf"))
+                    continue
+                for s in range(2):
+                    C.csrc_spmv(mats[s % ncopy], p, xs[s % ncopy], ys[s % ncopy])
+                runs = []
+                for _ in range(3):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for s in range(args.reps):
+                        C.csrc_spmv(mats[s % ncopy], p, xs[s % ncopy], ys[s % ncopy])
+                    e1.record()
+                    torch.cuda.synchronize()
+                    runs.append(e0.elapsed_time(e1) * 1e3 / args.reps)
+                times.append(float(np.median(runs)))
+            rec = {"m": m, "spec": spec, "n": host["n"], "nnz": 2 * host["k"] + host["n"],
+                   "features": [float(v) for v in f], "times_us": times, "best": int(np.argmin(times)),
+                   "candidates": [T.candidate_name(i) for i in range(len(T.CANDIDATES))]}
+            out.write(json.dumps(rec) + "\n")
+            out.flush()
+            count += 1
+            if count % 25 == 0:
+                print(f"# {count} matrices, {time.time() - t0:.0f}s", flush=True)
+            del plans, mats, xs, ys, A
+            if time.time() - t0 > args.budget:
+                print(f"# budget reached after {count} matrices", flush=True)
+                queue.clear()
+                break
+    pool.shutdown(wait=False, cancel_futures=True)
+    threads.shutdown(wait=False)
+    print(f"# campaign piece done: {count} matrices in {time.time() - t0:.0f}s", flush=True)
+
+
+def load_db(path):
+    recs = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip():
+                r = json.loads(line)
+                recs[r["m"]] = r
+    return [recs[m] for m in sorted(recs)]
+
+
+def evaluate(model, recs, default):
+    """Regret of the model's picks against exhaustive tuning, and its gain
+    over the fixed default candidate, on the given records."""
+    ratio, gain, hit = [], [], 0
+    for r in recs:
+        t = np.array(r["times_us"])
+        pick = model.predict(np.array(r["features"], dtype=np.float32))
+        best = t.min()
+        tp = t[pick] if np.isfinite(t[pick]) else t[default]
+        ratio.append(tp / best)
+        gain.append(t[default] / tp)
+        hit += int(pick == int(np.argmin(t)))
+    ratio = np.array(ratio)
+    gain = np.array(gain)
+    return {"matrices": len(recs), "exact_pick_rate": hit / max(1, len(recs)),
+            "regret_mean": float(ratio.mean() - 1), "regret_median": float(np.median(ratio) - 1),
+            "regret_geomean": float(np.exp(np.log(ratio).mean()) - 1), "regret_max": float(ratio.max() - 1),
+            "gain_vs_default_geomean": float(np.exp(np.log(gain).mean())),
+            "time_total_model_over_default": float(sum(np.array(r["times_us"])[default] for r in recs) /
+                                                    sum(np.array(r["times_us"])[model.predict(
+                                                        np.array(r["features"], dtype=np.float32))]
+                                                        if np.isfinite(np.array(r["times_us"])[model.predict(
+                                                            np.array(r["features"], dtype=np.float32))])
+                                                        else np.array(r["times_us"])[default] for r in recs))}
+
+
+def train_cmd(args):
+    import torch
+    from paper_1003_0952_amd import selector as S, tuner as T
+    recs = load_db(args.db)
+    train_r = [r for r in recs if r["m"] < args.heldout_from]
+    test_r = [r for r in recs if r["m"] >= args.heldout_from]
+    F = np.array([r["features"] for r in train_r], dtype=np.float32)
+    y = np.array([r["best"] for r in train_r], dtype=np.int32)
+    K = len(T.CANDIDATES)
+    t0 = time.time()
+    params, mean, scale, hist = S.train(torch, F, y, K, steps=args.steps, lr=args.lr, seed=args.seed)
+    model = S.Selector(params, mean, scale)
+    rep = {"train_matrices": len(train_r), "heldout_matrices": len(test_r), "steps": args.steps,
+           "train_seconds": round(time.time() - t0, 2), "loss_first": hist[0], "loss_last": hist[-1],
+           "label_histogram": np.bincount(y, minlength=K).tolist(),
+           "candidates": [T.candidate_name(i) for i in range(K)], "default": T.candidate_name(T.DEFAULT),
+           "train": evaluate(model, train_r, T.DEFAULT), "heldout": evaluate(model, test_r, T.DEFAULT)}
+    os.makedirs(os.path.dirname(args.model), exist_ok=True)
+    model.save(args.model)
+    with open(args.report, "w") as fh:
+        json.dump(rep, fh, indent=1)
+    print(json.dumps(rep["heldout"]), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("campaign")
+    c.add_argument("--count", type=int, default=2000)
+    c.add_argument("--db", default=os.path.join(DATA, "timings.jsonl"))
+    c.add_argument("--nnz-cap", type=float, default=2e6)
+    c.add_argument("--workers", type=int, default=10)
+    c.add_argument("--reps", type=int, default=5)
+    c.add_argument("--budget", type=float, default=480)
+    t = sub.add_parser("train")
+    t.add_argument("--db", default=os.path.join(DATA, "timings.jsonl"))
+    t.add_argument("--model", default=os.path.join(DATA, "model.json"))
+    t.add_argument("--report", default=os.path.join(DATA, "report.json"))
+    t.add_argument("--heldout-from", type=int, default=1800)
+    t.add_argument("--steps", type=int, default=3000)
+    t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.cmd == "campaign":
+        campaign(args)
+    else:
+        train_cmd(args)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(HERE))
+    main()

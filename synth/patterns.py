@@ -240,16 +240,10 @@ def permute(a, order):
 
 
 def random_order(n, seed):
-    """Seeded uniform random permutation (Fisher-Yates on counter uniforms)."""
-    order = np.arange(n, dtype=np.int64)
+    """Seeded uniform random permutation: rows sorted by a counter-based
+    uniform key (53 random bits each; ties broken by index)."""
     u = uniform01(seed, 21, np.arange(n, dtype=np.int64))
-    # Fisher-Yates: step t swaps position t with a uniform position in [t, n).
-    j = (np.arange(n) + np.floor(u * (n - np.arange(n)))).astype(np.int64)
-    j = np.minimum(j, n - 1)
-    for t in range(n - 1):
-        jt = j[t]
-        order[t], order[jt] = order[jt], order[t]
-    return order
+    return np.argsort(u, kind="stable").astype(np.int64)
 
 
 def rcm_order(a):

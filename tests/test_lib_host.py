@@ -216,3 +216,29 @@ def test_features_definition():
     fill_values(t, 1)
     ct = R.csr_to_csrc(t.n, t.rowptr, t.col, t.val)
     assert C.csrc_features(ct["ia"], ct["ja"], "f64", 3)[11] == 1.0
+
+
+def test_features_oracle_hand_values():
+    # 1D Laplacian pattern on 6 rows: lower pairs (i, i-1); lengths 2,3,3,3,3,2
+    from oracle import features as OF
+    n = 6
+    rows = [i for i in range(n) for _ in (0,)] + list(range(1, n)) + list(range(0, n - 1))
+    cols = list(range(n)) + list(range(0, n - 1)) + list(range(1, n))
+    key = np.unique(np.array(rows) * n + np.array(cols))
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(key // n, minlength=n), out=rp[1:])
+    c = R.csr_to_csrc(n, rp, key % n, np.ones(key.size))
+    f = OF.features(c)
+    assert f[0] == np.log2(7) and f[1] == np.log2(17)
+    assert f[2] == pytest.approx(16 / 6) and f[4] == pytest.approx(3 / (16 / 6))
+    assert f[5] == pytest.approx(1 / 6) and f[6] == pytest.approx(1 / 6) and f[7] == 1.0
+    assert f[8] == np.log2(3.0) and f[9] == 2 / 32 and f[11] == 0.0
+
+
+@pytest.mark.parametrize("make", MATS)
+def test_features_match_oracle(make):
+    from oracle import features as OF
+    a = make()
+    c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+    got = C.csrc_features(c["ia"], c["ja"], "f64", -1)
+    assert np.allclose(got, OF.features(c), rtol=2e-6, atol=1e-6)
