@@ -112,14 +112,27 @@ def time_plan(C, torch, cp, plan, steps, warmup, per_product=False):
     return total / steps, prod
 
 
-CANDIDATES = [
-    ("private", dict(tile_work=8192, block=512)),
-    ("private", dict(tile_work=4096, block=256)),
-    ("private", dict(tile_work=4096, block=512)),
-    ("owner", dict(tile_work=16384, block=512)),
-    ("atomic", dict(tile_work=8192, block=512)),
-    ("color", dict()),
-]
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("csrc_spmv.hip", "csrc_plan.cpp", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1003_0952_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, dtype, vname, vkw):
+    """HBM bytes per product from the committed rocprofv3 counter summary, if it
+    was taken on this kernel source and configuration; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{dtype}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash() or d.get("variant") != vname or \
+            any(d.get("options", {}).get(k) != v for k, v in vkw.items()):
+        return None
+    return d["bytes_per_product"]
 
 
 def cpu_baseline(host, x, budget_s=12.0):
@@ -174,22 +187,37 @@ def main():
     print(f"# setup {time.perf_counter() - t_setup:.1f}s n={n} k={k} bytes/product={B1} copies={ncopy}",
           file=sys.stderr, flush=True)
 
-    # --- variant choice (outside the timed region)
-    chosen = None
+    # --- variant choice (outside the timed region): the learned selector's
+    # pick; the exhaustive tuner runs beside it to report the regret
+    from paper_1003_0952_amd import tuner as T, selector as S
+    selection = {}
     tuning = []
     if args.variant == "auto":
-        for v, kw in CANDIDATES:
+        tuned = None
+        for i, (v, kw) in enumerate(T.CANDIDATES):
+            if v in ("plain",):
+                continue
             try:
                 plan = C.Plan(cp.mats[0], v, **kw)
             except C.CsrcError as e:
-                tuning.append({"variant": v, **kw, "error": str(e)})
+                tuning.append({"candidate": T.candidate_name(i), "error": str(e)})
                 continue
             ms, _ = time_plan(C, torch, cp, plan, args.tune_steps, 3)
-            tuning.append({"variant": v, **kw, "ms_per_step": round(ms, 4)})
-            print(f"# tune {v} {kw} {ms:.4f} ms/step", file=sys.stderr, flush=True)
-            if chosen is None or ms < chosen[2]:
-                chosen = (v, kw, ms)
-        vname, vkw = chosen[0], chosen[1]
+            tuning.append({"candidate": T.candidate_name(i), "ms_per_step": round(ms, 4)})
+            print(f"# tune {T.candidate_name(i)} {ms:.4f} ms/step", file=sys.stderr, flush=True)
+            if tuned is None or ms < tuned[1]:
+                tuned = (i, ms)
+            del plan
+        model = S.Selector.load()
+        if model is not None:
+            pick = model.predict(C.csrc_features(host["ia"], host["ja"], args.dtype))
+            selection = {"by": "learned selector", "candidate": T.candidate_name(pick),
+                         "tuned_best": T.candidate_name(tuned[0])}
+        else:
+            pick = tuned[0]
+            selection = {"by": "exhaustive tuner", "candidate": T.candidate_name(pick)}
+        vname, vkw = T.CANDIDATES[pick][0], dict(T.CANDIDATES[pick][1])
+        tuned_ms = tuned[1]
     else:
         vname = args.variant
         vkw = {}
@@ -237,6 +265,9 @@ def main():
                "gflops": round(2 * flops(n, k) / dt / 1e9, 3)}
 
     ach = B1 / (per_prod_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.dtype, vname, vkw)
+    if selection and "tuned_best" in selection:
+        selection["regret_vs_tuned"] = round(ms / tuned_ms - 1.0, 4)
     out = {
         "metric": METRIC,
         "value": round(gbs, 1),
@@ -260,10 +291,11 @@ def main():
         "max_rel_err_vs_oracle": float(err),
         "plain_fp64": plain,
         "speedup_vs_plain": round(plain["ms_per_step"] / ms, 3) if plain else None,
+        "selection": selection,
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"{vname} product", "bytes_per_launch": B1},
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": f"{vname} product (all its launches)", "bytes_per_launch": B1},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

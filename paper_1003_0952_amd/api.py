@@ -10,7 +10,7 @@ import ctypes
 import numpy as np
 
 from . import binding as B
-from .binding import check, np_ptr, t_ptr, stream_ptr
+from .binding import check, np_ptr, t_ptr, stream_ptr, CsrcError  # noqa: F401
 
 _DT_NP = {B.F64: np.float64, B.F32_: np.float32, B.BF16: np.uint16}
 

@@ -131,30 +131,33 @@ def load_db(path):
     return [recs[m] for m in sorted(recs)]
 
 
-def evaluate(model, recs, default):
-    """Regret of the model's picks against exhaustive tuning, and its gain
-    over the fixed default candidate, on the given records."""
-    ratio, gain, hit = [], [], 0
+def baseline_pick(times, default, fallback):
+    """The choice without a selector: the default candidate, or the fallback
+    where the default cannot run the matrix."""
+    return default if np.isfinite(times[default]) else fallback
+
+
+def evaluate(model, recs, default, fallback):
+    """Regret of the model's picks against exhaustive tuning, and their gain
+    over the fixed choice without a selector, on the given records."""
+    ratio, gain, hit, t_model, t_base = [], [], 0, 0.0, 0.0
     for r in recs:
         t = np.array(r["times_us"])
         pick = model.predict(np.array(r["features"], dtype=np.float32))
-        best = t.min()
-        tp = t[pick] if np.isfinite(t[pick]) else t[default]
-        ratio.append(tp / best)
-        gain.append(t[default] / tp)
+        tp = t[pick] if np.isfinite(t[pick]) else t[baseline_pick(t, default, fallback)]
+        tb = t[baseline_pick(t, default, fallback)]
+        ratio.append(tp / t.min())
+        gain.append(tb / tp)
         hit += int(pick == int(np.argmin(t)))
+        t_model += tp
+        t_base += tb
     ratio = np.array(ratio)
     gain = np.array(gain)
     return {"matrices": len(recs), "exact_pick_rate": hit / max(1, len(recs)),
             "regret_mean": float(ratio.mean() - 1), "regret_median": float(np.median(ratio) - 1),
             "regret_geomean": float(np.exp(np.log(ratio).mean()) - 1), "regret_max": float(ratio.max() - 1),
             "gain_vs_default_geomean": float(np.exp(np.log(gain).mean())),
-            "time_total_model_over_default": float(sum(np.array(r["times_us"])[default] for r in recs) /
-                                                    sum(np.array(r["times_us"])[model.predict(
-                                                        np.array(r["features"], dtype=np.float32))]
-                                                        if np.isfinite(np.array(r["times_us"])[model.predict(
-                                                            np.array(r["features"], dtype=np.float32))])
-                                                        else np.array(r["times_us"])[default] for r in recs))}
+            "gain_vs_default_total_time": float(t_base / t_model)}
 
 
 def train_cmd(args):
@@ -173,7 +176,9 @@ def train_cmd(args):
            "train_seconds": round(time.time() - t0, 2), "loss_first": hist[0], "loss_last": hist[-1],
            "label_histogram": np.bincount(y, minlength=K).tolist(),
            "candidates": [T.candidate_name(i) for i in range(K)], "default": T.candidate_name(T.DEFAULT),
-           "train": evaluate(model, train_r, T.DEFAULT), "heldout": evaluate(model, test_r, T.DEFAULT)}
+           "fallback": T.candidate_name(T.FALLBACK),
+           "train": evaluate(model, train_r, T.DEFAULT, T.FALLBACK),
+           "heldout": evaluate(model, test_r, T.DEFAULT, T.FALLBACK)}
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
     model.save(args.model)
     with open(args.report, "w") as fh:

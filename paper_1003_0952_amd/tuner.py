@@ -30,6 +30,7 @@ CANDIDATES = [
     ("plain", {}),
 ]
 DEFAULT = 1      # the fixed choice without a selector: private, 8192, 512 threads
+FALLBACK = 5     # ... or atomic, 8192, 512 threads where private cannot run
 
 
 def candidate_name(i):

@@ -1,0 +1,71 @@
+"""The trained selector on its stored campaign (timings measured on MI355X by
+paper_1003_0952_amd.train_selector, network trained on the GPU): what the
+network gains over the fixed choice without it, on held-out matrices."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1003_0952_amd import selector as S, tuner as T
+from paper_1003_0952_amd.train_selector import load_db, evaluate, baseline_pick
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1003_0952_amd",
+                    "selector_data")
+
+
+@pytest.fixture(scope="module")
+def stored():
+    recs = load_db(os.path.join(DATA, "timings.jsonl"))
+    model = S.Selector.load(os.path.join(DATA, "model.json"))
+    assert model is not None and model.K == len(T.CANDIDATES)
+    return recs, model
+
+
+def test_campaign_shape(stored):
+    recs, _ = stored
+    assert len(recs) == 2000
+    assert {r["m"] for r in recs} == set(range(2000))
+    fams = {r["spec"]["family"] for r in recs}
+    assert fams == {"stencil", "banded", "fem3", "power"}
+    for r in recs:
+        assert len(r["features"]) == 12 and len(r["times_us"]) == len(T.CANDIDATES)
+        assert r["best"] == int(np.argmin(r["times_us"]))
+
+
+def test_heldout_gain_over_fixed_choice(stored):
+    recs, model = stored
+    held = [r for r in recs if r["m"] >= 1800]
+    ev = evaluate(model, held, T.DEFAULT, T.FALLBACK)
+    assert ev["matrices"] == 200
+    assert ev["gain_vs_default_geomean"] > 1.03      # faster than the fixed choice
+    assert ev["regret_mean"] < 0.10                   # close to exhaustive tuning
+    assert ev["exact_pick_rate"] > 0.6
+    # the selector never picks a candidate that cannot run a held-out matrix
+    for r in held:
+        assert np.isfinite(r["times_us"][model.predict(np.array(r["features"], dtype=np.float32))])
+
+
+def test_report_matches_stored_data(stored):
+    recs, model = stored
+    with open(os.path.join(DATA, "report.json")) as fh:
+        rep = json.load(fh)
+    held = [r for r in recs if r["m"] >= 1800]
+    ev = evaluate(model, held, T.DEFAULT, T.FALLBACK)
+    assert rep["heldout"]["exact_pick_rate"] == pytest.approx(ev["exact_pick_rate"])
+    assert rep["heldout"]["gain_vs_default_geomean"] == pytest.approx(ev["gain_vs_default_geomean"])
+
+
+@pytest.mark.parametrize("m", [1800, 1803, 1950])
+def test_stored_features_are_the_library_features(stored, m):
+    from synth import workloads as W
+    import paper_1003_0952_amd as C
+    recs, _ = stored
+    rec = next(r for r in recs if r["m"] == m)
+    spec = W.family_spec(m, nnz_cap=2e6)
+    assert spec == rec["spec"]
+    a, _ = W.family_member(spec)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    f = C.csrc_features(host["ia"], host["ja"], "f64", -1)
+    assert np.allclose(f, rec["features"], rtol=1e-6)
