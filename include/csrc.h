@@ -175,6 +175,13 @@ typedef struct csrc_plan_opts {
     int32_t compensated;      /* 1: compensated (TwoSum) accumulation of
                                  partial sums in the merge; reduced precision  */
     int32_t max_rhs;          /* largest r later passed to csrc_spmm (>= 1)   */
+    int32_t persistent;       /* PRIVATE, one right-hand side: 1 = persistent
+                                 workgroups that stream their tiles back to
+                                 back, staging tile t+1 while t streams (needs
+                                 block 512); 0 = one workgroup per tile       */
+    int32_t grid;             /* workgroups of the persistent launch (>= 8, one
+                                 tile range per XCD); 0 = as many as fit on
+                                 the device at once                           */
 } csrc_plan_opts;
 
 /* Fills opts with the defaults of a variant. */

@@ -127,7 +127,7 @@ class Plan:
 
     def __init__(self, A, variant="private", tile_work=0, lanes=0, block=0,
                  color_criterion=B.COLOR_WRITE_SET, ydtype="f32", compensated=False,
-                 max_rhs=1, stream=None):
+                 max_rhs=1, persistent=0, grid=0, stream=None):
         import torch
         self.variant = _variant(variant)
         opts = B.PlanOpts()
@@ -139,6 +139,8 @@ class Plan:
         opts.ydtype = _dt(ydtype)
         opts.compensated = 1 if compensated else 0
         opts.max_rhs = int(max_rhs)
+        opts.persistent = int(persistent)
+        opts.grid = int(grid)
         h = ctypes.c_void_p(0)
         check(B.lib.csrc_plan_create(A.n, np_ptr(A.host_ia), np_ptr(A.host_ja), A.vdtype,
                                      ctypes.byref(opts), ctypes.byref(h)), "csrc_plan_create")

@@ -120,6 +120,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
     if (o.block != 0 && (o.block < 64 || o.block > 512 || o.block % 64)) return CSRC_ERR_ARG;
     if (o.lanes != 0 && (o.lanes < 1 || o.lanes > 64 || (o.lanes & (o.lanes - 1)))) return CSRC_ERR_ARG;
     if (o.tile_work < 0 || o.max_rhs < 0 || o.max_rhs > csrc::kMaxRhs) return CSRC_ERR_ARG;
+    if (o.persistent < 0 || o.persistent > 1 || o.grid < 0 || (o.grid > 0 && o.grid < 8)) return CSRC_ERR_ARG;
+    if (o.persistent && (o.variant != CSRC_V_PRIVATE || (o.block != 0 && o.block != 512))) return CSRC_ERR_ARG;
     if (vdtype != CSRC_F64 && o.ydtype != CSRC_F32 && o.ydtype != CSRC_F64) return CSRC_ERR_ARG;
     *out = nullptr;
     csrc_plan *p = nullptr;
@@ -217,6 +219,10 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             }
             p->lds_bytes = csrc::lds_private(p->max_tile_rows, p->max_window, p->max_tile_entries,
                                              p->max_intervals, acc);
+            if (p->o.persistent) {
+                // two staging buffers
+                p->lds_bytes = 2 * csrc::align16(p->lds_bytes);
+            }
             if (p->o.max_rhs > 1)
                 p->lds_bytes = std::max(p->lds_bytes,
                                         csrc::lds_private_mm(p->max_tile_rows, p->max_window, p->max_tile_entries,

@@ -141,60 +141,70 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 
 constexpr uint32_t kNoRow = 0xFFFF;
 
-template <bool NT, class T>
-__device__ __forceinline__ T vload(const T *p)
+// Buffer descriptor over n bytes at p (raw addressing, stride 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes)
 {
-    if (NT) return __builtin_nontemporal_load(p);
-    return *p;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
 }
 
-// two consecutive entries starting at q (q even); elements at or past kend
-// are not read (zero)
-template <bool NT>
-__device__ __forceinline__ void pair(const int32_t *p, int64_t q, int64_t kend, int (&o)[2])
-{
-    if (q + 1 < kend) {
-        i2v v = vload<NT>(reinterpret_cast<const i2v *>(p + q));
-        o[0] = v.x; o[1] = v.y;
-    } else {
-        o[0] = q < kend ? p[q] : 0;
-        o[1] = 0;
+// The stored entries [kb, ke) of ja, al and au (kb even) behind buffer
+// descriptors.  Raw buffer loads check every dword against the descriptor
+// size: a dword at or past entry ke reads as zero and touches no memory.  So
+// a pair load at an even q needs no tail branch (a branch whose else-path
+// loads makes the compiler drain every outstanding load before the next
+// one), never reads past the range, and entries past ke come back as zero.
+// NT marks data read once (non-temporal).
+template <class VT, bool NT>
+struct Entries {
+    using V = typename VT::V;
+    using A = typename VT::A;
+    static constexpr int kAux = NT ? 2 : 0;
+    __amdgpu_buffer_rsrc_t rj, ra, ru;
+    int kb, ke;
+
+    __device__ __forceinline__ Entries(const int32_t *ja, const V *al, const V *au, int kb_, int ke_)
+        : kb(kb_), ke(ke_)
+    {
+        const uint32_t n = (uint32_t)max(ke_ - kb_, 0);
+        rj = make_rsrc(ja + kb_, n * 4u);
+        ra = make_rsrc(al + kb_, n * (uint32_t)sizeof(V));
+        ru = make_rsrc(au + kb_, n * (uint32_t)sizeof(V));
     }
-}
-template <bool NT>
-__device__ __forceinline__ void pair(const double *p, int64_t q, int64_t kend, double (&o)[2])
-{
-    if (q + 1 < kend) {
-        d2v v = vload<NT>(reinterpret_cast<const d2v *>(p + q));
-        o[0] = v.x; o[1] = v.y;
-    } else {
-        o[0] = q < kend ? p[q] : 0.0;
-        o[1] = 0.0;
+
+    __device__ __forceinline__ void j2(int q, int (&o)[2]) const
+    {
+        const i2v v = __builtin_bit_cast(i2v, __builtin_amdgcn_raw_buffer_load_b64(rj, (q - kb) * 4, 0, kAux));
+        o[0] = v.x;
+        o[1] = v.y;
     }
-}
-template <bool NT>
-__device__ __forceinline__ void pair(const float *p, int64_t q, int64_t kend, float (&o)[2])
-{
-    if (q + 1 < kend) {
-        f2v v = vload<NT>(reinterpret_cast<const f2v *>(p + q));
-        o[0] = v.x; o[1] = v.y;
-    } else {
-        o[0] = q < kend ? p[q] : 0.f;
-        o[1] = 0.f;
+    __device__ __forceinline__ void v2(__amdgpu_buffer_rsrc_t r, int q, double (&o)[2]) const
+    {
+        const d2v v = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (q - kb) * 8, 0, kAux));
+        o[0] = v.x;
+        o[1] = v.y;
     }
-}
-template <bool NT>
-__device__ __forceinline__ void pair(const uint16_t *p, int64_t q, int64_t kend, float (&o)[2])
-{
-    if (q + 1 < kend) {
-        const uint32_t v = vload<NT>(reinterpret_cast<const uint32_t *>(p + q));
-        o[0] = __uint_as_float(v << 16);
-        o[1] = __uint_as_float(v & 0xFFFF0000u);
-    } else {
-        o[0] = q < kend ? ldv(p, q) : 0.f;
-        o[1] = 0.f;
+    __device__ __forceinline__ void v2(__amdgpu_buffer_rsrc_t r, int q, float (&o)[2]) const
+    {
+        if constexpr (std::is_same<V, float>::value) {
+            const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, (q - kb) * 4, 0, kAux));
+            o[0] = v.x;
+            o[1] = v.y;
+        } else {
+            // bfloat16: one dword holds the pair; a dword that ends past the
+            // range reads as zero, so the lane whose pair straddles ke takes
+            // its first element from a 2-byte load (other lanes pass an
+            // offset outside the range: no memory access).
+            const int off = (q - kb) * 2;
+            const bool straddle = q + 1 == ke;
+            const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kAux);
+            const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, straddle ? off : 0x7FFFFFF0, 0, kAux);
+            o[0] = __uint_as_float((straddle ? (uint32_t)h : (w & 0xFFFFu)) << 16);
+            o[1] = __uint_as_float(w & 0xFFFF0000u);
+        }
     }
-}
+    __device__ __forceinline__ void al2(int q, A (&o)[2]) const { v2(ra, q, o); }
+    __device__ __forceinline__ void au2(int q, A (&o)[2]) const { v2(ru, q, o); }
+};
 
 // Fill s_rid[q - kb] = row - ra for the entries of rows [ra, rb), i.e.
 // [ia[ra], ia[rb]), and kNoRow on [kb, ia[ra]) and on [ia[rb], round2(...) + 2)
@@ -214,8 +224,9 @@ __device__ __forceinline__ void fill_row_ids(const int32_t *__restrict__ ia, int
     }
 }
 
-// One lane's share of a batch: pairs at qb and qb + 2B.
-// LOAD_AL / LOAD_AU select which value arrays are fetched up front.
+// One lane's share of a batch: pairs at qb and qb + 2B of the entries E.
+// LOAD_AL / LOAD_AU select which value arrays are fetched up front (the
+// others read as zero).  Pairs past the range of E read as zero.
 template <class VT, bool LOAD_AL, bool LOAD_AU, bool NT>
 struct Batch {
     using A = typename VT::A;
@@ -224,25 +235,31 @@ struct Batch {
     A a[2][2];
     A u[2][2];
 
-    __device__ __forceinline__ void load(int qb, int k1, int64_t kend, const int32_t *__restrict__ ja,
-                                         const V *__restrict__ al, const V *__restrict__ au)
+    __device__ __forceinline__ void load(int qb, const Entries<VT, NT> &E)
     {
         const int half = 2 * (int)blockDim.x;
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int q = qb + half * s;
-            if (q < k1) {
-                pair<NT>(ja, q, kend, j[s]);
-                if (LOAD_AL) pair<NT>(al, q, kend, a[s]);
-                if (LOAD_AU) pair<NT>(au, q, kend, u[s]);
-            } else {
-                j[s][0] = j[s][1] = -1;
-                a[s][0] = a[s][1] = A(0);
-                u[s][0] = u[s][1] = A(0);
-            }
+            E.j2(q, j[s]);
+            if (LOAD_AL) E.al2(q, a[s]);
+            else a[s][0] = a[s][1] = A(0);
+            if (LOAD_AU) E.au2(q, u[s]);
+            else u[s][0] = u[s][1] = A(0);
         }
     }
 };
+
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// Wait for every outstanding memory operation.  Placed where everything has
+// landed anyway (after staging), it resets the compiler's per-register
+// pending-load state, which it otherwise merges conservatively over the
+// staging code's divergent paths and turns into waits on the next batch
+// inside the stream loop.
+__device__ __forceinline__ void settle_loads() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Stream entries [kb, k1) of the block (kb = k0 rounded down to even).  `cur`
 // holds the first batch, issued by the caller before its staging.  For each
@@ -250,20 +267,22 @@ struct Batch {
 // and gathers, and a lane's run of gathered products of one row goes to
 // flush(r, sum).  With LOAD_AU false, an au pair is fetched only if need_au(j)
 // holds for one of its entries (else its products are zero and ent ignores
-// them).
-template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush>
-__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, int kb, int k1, int64_t kend,
+// them).  The batch loop runs the same number of times in every lane (lanes
+// past k1 see only kNoRow), so after_first() is called once, by all lanes
+// together, after the first batch.
+template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush, class Hook = NoHook>
+__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, const Entries<VT, NT> &E,
                                            const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
-                                           const int32_t *__restrict__ ja,
-                                           const typename VT::V *__restrict__ al,
-                                           const typename VT::V *__restrict__ au, NeedAu need_au,
-                                           Ent ent, Flush flush)
+                                           NeedAu need_au, Ent ent, Flush flush, Hook after_first = Hook())
 {
     using A = typename VT::A;
     const int half = 2 * (int)blockDim.x;
-    for (int qb = kb + 2 * (int)threadIdx.x; qb < k1; qb += 2 * half) {
+    const int kb = E.kb, k1 = E.ke;
+    int base = kb;
+    do {
+        const int qb = base + 2 * (int)threadIdx.x;
         Batch<VT, true, LOAD_AU, NT> nxt;
-        if (qb + 2 * half < k1) nxt.load(qb + 2 * half, k1, kend, ja, al, au);
+        if (base + 2 * half < k1) nxt.load(qb + 2 * half, E);
         uint32_t rv[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -275,7 +294,7 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, in
             for (int s = 0; s < 2; ++s) {
                 const bool need = ((rv[s] & 0xFFFF) != kNoRow && need_au(cur.j[s][0])) ||
                                   ((rv[s] >> 16) != kNoRow && need_au(cur.j[s][1]));
-                if (need) pair<NT>(au, qb + half * s, kend, cur.u[s]);
+                if (need) E.au2(qb + half * s, cur.u[s]);
                 else cur.u[s][0] = cur.u[s][1] = A(0);
             }
         }
@@ -292,8 +311,10 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, in
                 if (r1 != (int)kNoRow) flush(r1, g1);
             }
         }
+        if (base == kb) after_first();
         cur = nxt;
-    }
+        base += 2 * half;
+    } while (base < k1);
 }
 
 // Stage a tile's own rows: s_x[i] = x_i and s_y[i] = ad_i x_i (the diagonal
@@ -337,13 +358,15 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = tiles[t], r1 = tiles[t + 1], T = r1 - r0;
     const int k0 = tile_k[t], k1 = tile_k[t + 1], kb = k0 & ~1;
+    const Entries<VT, true> E(ja, al, au, kb, k1);
     Batch<VT, true, true, true> first;
-    first.load(kb + 2 * tid, k1, kend, ja, al, au);
+    first.load(kb + 2 * tid, E);
     stage_rows<VT>(r0, T, ad, x, s_x, s_y, ldx);
     fill_row_ids(ia, r0, r1, kb, s_rid);
     __syncthreads();
+    settle_loads();
     own_stream<VT, true, true>(
-        first, kb, k1, kend, s_rid, s_x, ja, al, au, [](int) { return true; },
+        first, E, s_rid, s_x, [](int) { return true; },
         [&](int j, A w) -> A {
             if (j >= r0) {
                 atomic_add(&s_y[j - r0], w);
@@ -359,10 +382,140 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
 
 // ---------------------------------------------------------------- PRIVATE
 
+// What a tile needs before it can stream, held in registers until it is
+// written to LDS: its bounds, its own rows (x, diagonal, row starts; row
+// i = threadIdx.x + s * blockDim.x, s < S), its interval list (interval l in
+// lane l of every wave: at most 64 intervals) and its window x values (slot
+// threadIdx.x + s * blockDim.x, s < S).  Every load whose address is known is
+// issued at once, so a tile costs one dependent round trip (intervals, then
+// window x) instead of one per staging step.
+template <class VT, int S>
+struct NextTile {
+    using A = typename VT::A;
+    int r0, T, k0, k1, kb, e0, NI, W;
+    A xr[S], dr[S];
+    int q0[S], q1[S];
+    int ivrow, ivslot, ivend;
+    A xw[S];
+
+    // Issue every load of tile t whose address is known without waiting
+    // (intervals first: the window gather waits for them alone).
+    __device__ __forceinline__ void issue(const PlanDev &P, int t, const int32_t *__restrict__ ia,
+                                          const typename VT::V *__restrict__ ad,
+                                          const typename VT::X *__restrict__ x)
+    {
+        const int tid = threadIdx.x, lane = tid & 63, B = blockDim.x;
+        r0 = P.tiles[t];
+        T = P.tiles[t + 1] - r0;
+        k0 = P.tile_k[t];
+        k1 = P.tile_k[t + 1];
+        kb = k0 & ~1;
+        e0 = P.iv_ptr[t];
+        NI = P.iv_ptr[t + 1] - e0;
+        ivrow = 0;
+        ivslot = 0x7FFFFFFF;
+        ivend = 0;
+        if (lane < NI) {
+            ivrow = P.iv_row[e0 + lane];
+            ivslot = P.iv_slot[e0 + lane];
+            ivend = ivslot + P.iv_len[e0 + lane];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tid + s * B;
+            if (i < T) {
+                xr[s] = (A)x[r0 + i];
+                dr[s] = (A)ldv(ad, r0 + i);
+                q0[s] = ia[r0 + i];
+                q1[s] = ia[r0 + i + 1];
+            }
+        }
+    }
+
+    // Row of window slot sl: the slot lies in the last interval whose first
+    // slot is <= sl, found by a binary search over the lanes (every lane of
+    // the wave takes part).
+    __device__ __forceinline__ int window_row(int sl) const
+    {
+        int k = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int c = k + step;
+            const int sc = __shfl(ivslot, c & 63);
+            if (c < NI && sc <= sl) k = c;
+        }
+        return __shfl(ivrow, k) + (sl - __shfl(ivslot, k));
+    }
+
+    // Window x loads of the first S blockDim.x slots (needs the intervals).
+    __device__ __forceinline__ void window(const typename VT::X *__restrict__ x)
+    {
+        const int tid = threadIdx.x, B = blockDim.x;
+        W = __shfl(ivend, NI > 0 ? NI - 1 : 0);
+        if (NI == 0) W = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int sl = tid + s * B;
+            const int row = window_row(sl);
+            if (sl < W) xw[s] = (A)x[row];
+        }
+    }
+
+    // Write the tile into LDS (layout of k_private).  Rows and slots past
+    // the first S blockDim.x are loaded here.  Every thread calls it.
+    __device__ __forceinline__ void stage(const int32_t *__restrict__ ia, const typename VT::V *__restrict__ ad,
+                                          const typename VT::X *__restrict__ x, A *s_x, A *s_y, A *s_xw, A *s_w,
+                                          uint16_t *s_rid, int32_t *s_ivrow) const
+    {
+        const int tid = threadIdx.x, B = blockDim.x;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tid + s * B;
+            if (i < T) {
+                s_x[i] = xr[s];
+                s_y[i] = dr[s] * xr[s];
+                for (int q = q0[s]; q < q1[s]; ++q) s_rid[q - kb] = (uint16_t)i;
+            }
+        }
+        for (int i = tid + S * B; i < T; i += B) {
+            const A xv = (A)x[r0 + i];
+            s_x[i] = xv;
+            s_y[i] = (A)ldv(ad, r0 + i) * xv;
+            const int b = ia[r0 + i], e = ia[r0 + i + 1];
+            for (int q = b; q < e; ++q) s_rid[q - kb] = (uint16_t)i;
+        }
+        const int len = ((k1 - kb) + 3) & ~1;
+        for (int q = tid; q < k0 - kb; q += B) s_rid[q] = kNoRow;
+        for (int q = (k1 - kb) + tid; q < len; q += B) s_rid[q] = kNoRow;
+        if (tid < NI) {
+            s_ivrow[tid] = ivrow;
+            s_ivrow[NI + tid] = ivslot;
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int sl = tid + s * B;
+            if (sl < W) {
+                s_xw[sl] = xw[s];
+                s_w[sl] = A(0);
+            }
+        }
+        for (int base = S * B; base < W; base += B) {
+            const int sl = base + tid;
+            const int row = window_row(sl);
+            if (sl < W) {
+                s_xw[sl] = (A)x[row];
+                s_w[sl] = A(0);
+            }
+        }
+    }
+};
+
+
 // Local buffers of Sec. 3.1 kept in LDS: a tile of rows [r0, r1) accumulates
 // its own rows (s_y) and its effective range below r0 (s_w, compact window
 // slots).  x of both ranges is staged in LDS first (s_x, s_xw).  Own rows go
-// to y; window slots go to the partial buffer for the merge pass.
+// to y; window slots go to the partial buffer for the merge pass.  All
+// staging loads and the first batch of entries are in flight together.
 template <class VT, class YT>
 __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
@@ -384,30 +537,20 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
 
     const int tid = threadIdx.x, B = blockDim.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
-    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
+    NextTile<VT, 2> nt;
+    nt.issue(P, t, ia, ad, x);
+    const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
     Batch<VT, true, true, true> first;
-    first.load(kb + 2 * tid, k1, kend, ja, al, au);
-
-    const int e0 = P.iv_ptr[t], NI = P.iv_ptr[t + 1] - e0;
-    int32_t *s_ivslot = s_ivrow + NI;
-    const int W = NI ? P.iv_slot[e0 + NI - 1] + P.iv_len[e0 + NI - 1] : 0;
-    stage_rows<VT>(r0, T, ad, x, s_x, s_y);
-    for (int i = tid; i < NI; i += B) {
-        s_ivrow[i] = P.iv_row[e0 + i];
-        s_ivslot[i] = P.iv_slot[e0 + i];
-    }
-    fill_row_ids(ia, r0, r1, kb, s_rid);
+    first.load(nt.kb + 2 * tid, E);
+    nt.window(x);
+    nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
+    const int r0 = nt.r0, T = nt.T, e0 = nt.e0, NI = nt.NI, W = nt.W;
+    const int32_t *s_ivslot = s_ivrow + NI;
     __syncthreads();
-    for (int sl = tid; sl < W; sl += B) {
-        const int k = upper_index(s_ivslot, NI, sl);
-        s_xw[sl] = (A)x[s_ivrow[k] + (sl - s_ivslot[k])];
-        s_w[sl] = A(0);
-    }
-    __syncthreads();
+    settle_loads();
 
     own_stream<VT, true, true>(
-        first, kb, k1, kend, s_rid, s_x, ja, al, au, [](int) { return true; },
+        first, E, s_rid, s_x, [](int) { return true; },
         [&](int j, A w) -> A {
             if (j >= r0) {
                 atomic_add(&s_y[j - r0], w);
@@ -425,6 +568,117 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     if (W) {
         A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0];
         for (int sl = tid; sl < W; sl += B) part[sl] = s_w[sl];
+    }
+}
+
+// ----------------------------------------------------- PRIVATE, persistent
+
+// PRIVATE with persistent workgroups (512 threads).  XCD x (workgroups
+// b = x mod 8) owns the contiguous tile range [x ntiles / 8, (x+1) ntiles / 8)
+// and its workgroups take those tiles in turn.  Two LDS buffers alternate:
+// while tile t streams out of one, the loads of tile t+1 (rows, intervals,
+// window x and its first batch) are in flight, and tile t+1 is written into
+// the other buffer as soon as t's stream ends, so the memory pipe does not
+// drain between tiles.  Per tile the arithmetic is that of k_private.
+// Each thread prefetches S rows and S window slots of the next tile.
+template <class VT, class YT, int S>
+__global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int64_t kend,
+                                                   const int32_t *__restrict__ ia,
+                                                   const int32_t *__restrict__ ja,
+                                                   const typename VT::V *__restrict__ ad,
+                                                   const typename VT::V *__restrict__ al,
+                                                   const typename VT::V *__restrict__ au,
+                                                   const typename VT::X *__restrict__ x,
+                                                   YT *__restrict__ y, int tmax, int wmax, int emax,
+                                                   int buf_bytes)
+{
+    using A = typename VT::A;
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int X = 8;
+    const int tid = threadIdx.x;
+    const int xcd = blockIdx.x % X, slot = blockIdx.x / X;
+    const int nslot = ((int)gridDim.x - xcd + X - 1) / X;
+    const int hi = (int)((int64_t)(xcd + 1) * ntiles / X);
+    int t = (int)((int64_t)xcd * ntiles / X) + slot;
+    if (t >= hi) return;
+
+    auto buffers = [&](int c, A *&s_x, A *&s_y, A *&s_xw, A *&s_w, uint16_t *&s_rid, int32_t *&s_iv) {
+        unsigned char *b = lds + (size_t)c * buf_bytes;
+        s_x = reinterpret_cast<A *>(b);
+        s_y = s_x + tmax;
+        s_xw = s_y + tmax;
+        s_w = s_xw + wmax;
+        s_rid = reinterpret_cast<uint16_t *>(b + align16((2 * (int64_t)tmax + 2 * wmax) * sizeof(A)));
+        s_iv = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
+                                           align16(((int64_t)emax + 4) * 2));
+    };
+
+    NextTile<VT, S> nt;
+    Batch<VT, true, true, true> cur;
+    nt.issue(P, t, ia, ad, x);
+    cur.load(nt.kb + 2 * tid, Entries<VT, true>(ja, al, au, nt.kb, nt.k1));
+    nt.window(x);
+    {
+        A *s_x, *s_y, *s_xw, *s_w;
+        uint16_t *s_rid;
+        int32_t *s_iv;
+        buffers(0, s_x, s_y, s_xw, s_w, s_rid, s_iv);
+        nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_iv);
+    }
+    __syncthreads();
+
+    for (int c = 0;; c ^= 1) {
+        settle_loads();
+        // the tile about to stream
+        const int r0 = nt.r0, T = nt.T, e0 = nt.e0, NI = nt.NI, W = nt.W;
+        const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
+        A *s_x, *s_y, *s_xw, *s_w;
+        uint16_t *s_rid;
+        int32_t *s_ivrow;
+        buffers(c, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
+        const int32_t *s_ivslot = s_ivrow + NI;
+
+        const int tn = t + nslot;
+        const bool more = tn < hi;
+        Batch<VT, true, true, true> nb;
+        if (more) {
+            nt.issue(P, tn, ia, ad, x);
+            nb.load(nt.kb + 2 * tid, Entries<VT, true>(ja, al, au, nt.kb, nt.k1));
+        }
+        own_stream<VT, true, true>(
+            cur, E, s_rid, s_x, [](int) { return true; },
+            [&](int j, A w) -> A {
+                if (j >= r0) {
+                    atomic_add(&s_y[j - r0], w);
+                    return s_x[j - r0];
+                }
+                const int k = upper_index(s_ivrow, NI, j);
+                const int sl = s_ivslot[k] + (j - s_ivrow[k]);
+                atomic_add(&s_w[sl], w);
+                return s_xw[sl];
+            },
+            [&](int r, A v) { atomic_add(&s_y[r], v); },
+            [&]() {
+                if (more) nt.window(x);
+            });
+        __syncthreads();
+
+        for (int i = tid; i < T; i += 512) y[r0 + i] = (YT)s_y[i];
+        if (W) {
+            A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0];
+            for (int sl = tid; sl < W; sl += 512) part[sl] = s_w[sl];
+        }
+        if (!more) break;
+        {
+            A *n_x, *n_y, *n_xw, *n_w;
+            uint16_t *n_rid;
+            int32_t *n_iv;
+            buffers(c ^ 1, n_x, n_y, n_xw, n_w, n_rid, n_iv);
+            nt.stage(ia, ad, x, n_x, n_y, n_xw, n_w, n_rid, n_iv);
+        }
+        __syncthreads();
+        cur = nb;
+        t = tn;
     }
 }
 
@@ -485,13 +739,15 @@ __global__ __launch_bounds__(512) void k_owner(PlanDev P, int64_t kend, const in
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
     const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
+    const Entries<VT, false> E(ja, al, au, kb, k1);
     Batch<VT, true, false, false> first;
-    first.load(kb + 2 * tid, k1, kend, ja, al, au);
+    first.load(kb + 2 * tid, E);
     stage_rows<VT>(r0, T, ad, x, s_x, s_y);
     fill_row_ids(ia, r0, r1, kb, s_rid);
     __syncthreads();
+    settle_loads();
     own_stream<VT, false, false>(
-        first, kb, k1, kend, s_rid, s_x, ja, al, au, [&](int j) { return j >= r0; },
+        first, E, s_rid, s_x, [&](int j) { return j >= r0; },
         [&](int j, A w) -> A {
             if (j >= r0) {
                 atomic_add(&s_y[j - r0], w);
@@ -506,15 +762,17 @@ __global__ __launch_bounds__(512) void k_owner(PlanDev P, int64_t kend, const in
     for (int e = p0; e < p1; ++e) {
         const int pa = P.iv_row[e], L = P.iv_len[e];
         const int qa = ia[pa], qe = ia[pa + L], qbase = qa & ~1;
+        const Entries<VT, false> Ep(ja, al, au, qbase, qe);
         Batch<VT, false, false, false> cur;
-        cur.load(qbase + 2 * tid, qe, kend, ja, al, au);
+        cur.load(qbase + 2 * tid, Ep);
         __syncthreads();   // earlier readers of s_rid / s_xp are done
         for (int i = tid; i < L; i += B) s_xp[i] = (A)x[pa + i];
         fill_row_ids(ia, pa, pa + L, qbase, s_rid);
         __syncthreads();
+        settle_loads();
         for (int qb = qbase + 2 * tid; qb < qe; qb += 2 * half) {
             Batch<VT, false, false, false> nxt;
-            if (qb + 2 * half < qe) nxt.load(qb + 2 * half, qe, kend, ja, al, au);
+            if (qb + 2 * half < qe) nxt.load(qb + 2 * half, Ep);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int q = qb + half * s;
@@ -526,7 +784,7 @@ __global__ __launch_bounds__(512) void k_owner(PlanDev P, int64_t kend, const in
                 const bool t1 = rb != (int)kNoRow && j1 >= r0 && j1 < r1;
                 if (!(t0 || t1)) continue;
                 A uv[2];
-                pair<false>(au, q, kend, uv);
+                Ep.au2(q, uv);
                 if (t0) atomic_add(&s_y[j0 - r0], uv[0] * s_xp[ra]);
                 if (t1) atomic_add(&s_y[j1 - r0], uv[1] * s_xp[rb]);
             }
@@ -612,11 +870,13 @@ __device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, int64_t
             s_w[e] = A(0);
         }
         __syncthreads();
+        settle_loads();
+        const Entries<VT, false> E(ja, al, au, kb, k1);
         Batch<VT, true, true, false> cur;
-        cur.load(kb + 2 * tid, k1, kend, ja, al, au);
+        cur.load(kb + 2 * tid, E);
         for (int qb = kb + 2 * tid; qb < k1; qb += 2 * half) {
             Batch<VT, true, true, false> nxt;
-            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, k1, kend, ja, al, au);
+            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, E);
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp) {
                 const int q = qb + half * sp;
@@ -785,11 +1045,13 @@ __global__ __launch_bounds__(512) void k_owner_mm(PlanDev P, int64_t kend, const
         }
         fill_row_ids(ia, r0, r1, kb, s_rid);
         __syncthreads();
+        settle_loads();
+        const Entries<VT, false> E(ja, al, au, kb, k1);
         Batch<VT, true, true, false> cur;
-        cur.load(kb + 2 * tid, k1, kend, ja, al, au);
+        cur.load(kb + 2 * tid, E);
         for (int qb = kb + 2 * tid; qb < k1; qb += 2 * half) {
             Batch<VT, true, true, false> nxt;
-            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, k1, kend, ja, al, au);
+            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, E);
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp) {
                 const int q = qb + half * sp;
@@ -828,22 +1090,27 @@ __global__ __launch_bounds__(512) void k_owner_mm(PlanDev P, int64_t kend, const
             }
             fill_row_ids(ia, pa, pa + L, qbase, s_rid);
             __syncthreads();
+            settle_loads();
+            const Entries<VT, false> Ep(ja, al, au, qbase, qe);
             for (int qb = qbase + 2 * tid; qb < qe; qb += 2 * half) {
 #pragma unroll
                 for (int sp = 0; sp < 2; ++sp) {
                     const int q = qb + half * sp;
                     if (q >= qe) continue;
                     int jj[2];
-                    pair<false>(ja, q, kend, jj);
+                    A uu[2] = {A(0), A(0)};
+                    Ep.j2(q, jj);
                     const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - qbase));
+                    const bool t0 = (rv & 0xFFFF) != kNoRow && jj[0] >= r0 && jj[0] < r1;
+                    const bool t1 = (rv >> 16) != kNoRow && jj[1] >= r0 && jj[1] < r1;
+                    if (t0 || t1) Ep.au2(q, uu);
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const int row = (int)((rv >> (16 * h)) & 0xFFFF);
                         const int j = jj[h];
-                        if (row == (int)kNoRow || j < r0 || j >= r1) continue;
-                        const A u = (A)ldv(au, q + h);
+                        if (!(h ? t1 : t0)) continue;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) atomic_add(&s_y[(j - r0) * C + c], u * s_xp[row * C + c]);
+                        for (int c = 0; c < C; ++c) atomic_add(&s_y[(j - r0) * C + c], uu[h] * s_xp[row * C + c]);
                     }
                 }
             }
@@ -925,6 +1192,8 @@ static PlanDev plan_dev(const csrc_plan *p, void *ws)
     return d;
 }
 
+static int device_cus();
+
 static int fill_grid(int64_t count) { return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (count + 255) / 256)); }
 
 template <class VT, class YT, int G>
@@ -968,9 +1237,29 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         const int tmax = p->max_tile_rows, wmax = p->max_window, emax = p->max_tile_entries;
         if (single) {
             const size_t lds = (size_t)lds_private(tmax, wmax, emax, p->max_intervals, sizeof(Acc));
-            auto kern = k_private<VT, YT>;
-            if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
-            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, emax);
+            if (p->o.persistent) {
+                if (B != 512 || p->max_intervals > 64 || 2 * align16((int64_t)lds) > kLdsBudget)
+                    return CSRC_ERR_UNSUPPORTED;
+                const int buf = (int)align16((int64_t)lds);
+                auto kern = k_private_p<VT, YT, 2>;
+                if (set_lds((const void *)kern, 2 * (size_t)buf)) return CSRC_ERR_HIP;
+                int grid = p->o.grid > 0 ? p->o.grid : p->persistent_grid.load(std::memory_order_relaxed);
+                if (grid <= 0) {
+                    int per_cu = 0;
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 512,
+                                                                     2 * (size_t)buf) != hipSuccess ||
+                        per_cu < 1)
+                        per_cu = 1;
+                    grid = std::max(8, device_cus() * per_cu);
+                    p->persistent_grid.store(grid, std::memory_order_relaxed);
+                }
+                kern<<<grid, 512, 2 * (size_t)buf, s>>>(P, p->ntiles, A->k, A->ia, A->ja, ad, al, au, x, y, tmax,
+                                                       wmax, emax, buf);
+            } else {
+                auto kern = k_private<VT, YT>;
+                if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+                kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, emax);
+            }
             if (p->nmerge_blocks > 0 && p->window_slots > 0) {
                 if (std::is_same<YT, double>::value)
                     k_merge<Acc, YT, double, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);

@@ -1,6 +1,7 @@
 // Internal declarations shared by the host and device sources of libcsrc.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <cstddef>
 #include <vector>
@@ -111,6 +112,7 @@ struct csrc_plan {
     int64_t window_slots = 0;
     int64_t pulled_rows = 0;
     int64_t lds_bytes = 0;
+    mutable std::atomic<int> persistent_grid{0};  // resolved at the first persistent launch
     int32_t ncolors = 0;
     int32_t nmerge_blocks = 0;
     // host tables

@@ -15,8 +15,23 @@ from tests.helpers import small_cases, oracle_csrc, rel_inf
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "atomic", "private", "color", "owner"]
+VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_persistent"]
 TOL = 1e-12
+
+
+def make_plan(C, A, variant, **kw):
+    """Plan of a variant name; private_persistent is PRIVATE with persistent
+    workgroups (block 512)."""
+    if variant == "private_persistent":
+        try:
+            return C.Plan(A, "private", persistent=1, **kw)
+        except C.CsrcError as e:
+            # two LDS staging buffers must fit: only wide windows are refused
+            assert e.status == -9
+            single = C.Plan(A, "private", **kw).info()["lds_bytes"]
+            assert 2 * ((single + 15) // 16 * 16) > 160 * 1024
+            pytest.skip("two staging buffers exceed the LDS")
+    return C.Plan(A, variant, **kw)
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +43,7 @@ def torch_cuda():
 
 def run(torch, C, host, x, variant, transpose, dtype="f64", **kw):
     A = C.Matrix(host, dtype)
-    plan = C.Plan(A, variant, **kw)
+    plan = make_plan(C, A, variant, **kw)
     xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", A.xdtype)
     y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
     (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
@@ -110,7 +125,7 @@ def test_empty_matrix(torch_cuda):
     host = C.csrc_from_csr(0, [0], [], [])
     A = C.Matrix(host, "f64")
     for v in VARIANTS:
-        plan = C.Plan(A, v)
+        plan = make_plan(C, A, v)
         e = torch_cuda.zeros(0, dtype=torch_cuda.float64, device="cuda")
         C.csrc_spmv(A, plan, e, e)
 
@@ -124,8 +139,24 @@ def test_repeated_products_identical(torch_cuda):
     A = C.Matrix(host, "f64")
     xt = torch.from_numpy(x).cuda()
     for v in VARIANTS:
-        plan = C.Plan(A, v)
+        plan = make_plan(C, A, v)
         y1 = C.spmv(A, plan, xt).clone()
         y2 = C.spmv(A, plan, xt)
         torch.cuda.synchronize()
         assert rel_inf(y1.cpu().numpy(), y2.cpu().numpy()) <= 1e-15
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("tile_work,grid", [(300, 8), (700, 0), (1500, 24), (4000, 13)])
+def test_persistent_schedules(torch_cuda, case, tile_work, grid):
+    """Persistent PRIVATE over tile sizes and grids: several tiles per
+    workgroup, uneven tiles per XCD, grids that are not a multiple of 8."""
+    import paper_1003_0952_amd as C
+    name, a, x = CASES[case]
+    print(f"case {name} persistent tile_work {tile_work} grid {grid}", flush=True)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    for transpose in (False, True):
+        y, _ = run(torch_cuda, C, host, x, "private_persistent", transpose, tile_work=tile_work, grid=grid)
+        ref = (R.spmv_t if transpose else R.spmv)(c, x)
+        assert rel_inf(y, ref) <= TOL, (name, tile_work, grid, transpose, rel_inf(y, ref))

@@ -198,6 +198,31 @@ def test_plan_options_rejected():
         HostPlan(h, "private", lanes=3)
     with pytest.raises(C.CsrcError):
         HostPlan(h, "private", block=100)
+    # persistent workgroups: PRIVATE only, 512 threads, grid 0 or >= 8
+    for variant, kw in (("atomic", {}), ("owner", {}), ("private", {"block": 256}),
+                        ("private", {"grid": 3}), ("private", {"persistent": 2})):
+        kw = dict(kw)
+        kw.setdefault("persistent", 1)
+        with pytest.raises(C.CsrcError) as e:
+            HostPlan(h, variant, **kw)
+        assert e.value.status == -1, (variant, kw)
+
+
+@pytest.mark.parametrize("make", MATS[:5])
+def test_persistent_plan_doubles_lds(make):
+    """A persistent plan is the same tiling with two LDS staging buffers."""
+    c, h = host_matrix(make())
+    for work in (700, 4000):
+        one = HostPlan(h, "private", tile_work=work)
+        try:
+            two = HostPlan(h, "private", tile_work=work, persistent=1, grid=16)
+        except C.CsrcError as e:
+            assert e.status == -9
+            assert 2 * ((one.info()["lds_bytes"] + 15) // 16 * 16) > 160 * 1024
+            continue
+        assert np.array_equal(one.export(0), two.export(0))
+        assert np.array_equal(one.export(2), two.export(2))
+        assert two.info()["lds_bytes"] == 2 * ((one.info()["lds_bytes"] + 15) // 16 * 16)
 
 
 def test_features_definition():
