@@ -198,8 +198,9 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 p->max_intervals = std::max(p->max_intervals, (int32_t)iv.size());
             }
             p->window_slots = slots;
-            // merge lists: intervals touching each block of kMergeBlock rows,
-            // in ascending interval (= tile) order
+            // merge lists: for each block of kMergeBlock rows, the runs of
+            // its rows covered by each interval, in ascending interval (=
+            // tile) order
             int32_t nb = (n + csrc::kMergeBlock - 1) / csrc::kMergeBlock;
             p->nmerge_blocks = nb;
             p->mb_ptr.assign(nb + 1, 0);
@@ -210,12 +211,19 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 for (int32_t b = b0; b <= b1; ++b) p->mb_ptr[b + 1]++;
             }
             for (int32_t b = 0; b < nb; ++b) p->mb_ptr[b + 1] += p->mb_ptr[b];
-            p->mb_iv.resize(p->mb_ptr[nb]);
+            p->mb_seg.resize(p->mb_ptr[nb]);
             std::vector<int32_t> fill(p->mb_ptr.begin(), p->mb_ptr.end() - 1);
             for (int32_t g = 0; g < ni; ++g) {
-                int32_t b0 = p->iv_row[g] / csrc::kMergeBlock;
-                int32_t b1 = (p->iv_row[g] + p->iv_len[g] - 1) / csrc::kMergeBlock;
-                for (int32_t b = b0; b <= b1; ++b) p->mb_iv[fill[b]++] = g;
+                const int32_t a = p->iv_row[g], e = a + p->iv_len[g];
+                int32_t b0 = a / csrc::kMergeBlock;
+                int32_t b1 = (e - 1) / csrc::kMergeBlock;
+                for (int32_t b = b0; b <= b1; ++b) {
+                    csrc::MergeSeg sg;
+                    sg.lo = std::max(a, b * csrc::kMergeBlock);
+                    sg.hi = std::min(e, (b + 1) * csrc::kMergeBlock);
+                    sg.base = p->iv_goff[g] - a;
+                    p->mb_seg[fill[b]++] = sg;
+                }
             }
             p->lds_bytes = csrc::lds_private(p->max_tile_rows, p->max_window, p->max_tile_entries,
                                              p->max_intervals, acc);
@@ -303,7 +311,7 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         put(blob, p->t_iv_slot, p->iv_slot);
         put(blob, p->t_iv_goff, p->iv_goff);
         put(blob, p->t_mb_ptr, p->mb_ptr);
-        put(blob, p->t_mb_iv, p->mb_iv);
+        put(blob, p->t_mb_seg, p->mb_seg);
         put(blob, p->t_crow, p->crow);
         p->blob_bytes = (int64_t)blob.size();
         p->t_partials.offset = p->blob_bytes;

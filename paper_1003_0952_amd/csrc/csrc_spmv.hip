@@ -298,12 +298,20 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, co
                 else cur.u[s][0] = cur.u[s][1] = A(0);
             }
         }
+        // x of the entries' own rows, read before any LDS update of the batch
+        A xr[2][2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
+            xr[s][0] = s_x[r0 != (int)kNoRow ? r0 : 0];
+            xr[s][1] = s_x[r1 != (int)kNoRow ? r1 : 0];
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
             A g0 = A(0), g1 = A(0);
-            if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * s_x[r0]);
-            if (r1 != (int)kNoRow) g1 = cur.a[s][1] * ent(cur.j[s][1], cur.u[s][1] * s_x[r1]);
+            if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * xr[s][0]);
+            if (r1 != (int)kNoRow) g1 = cur.a[s][1] * ent(cur.j[s][1], cur.u[s][1] * xr[s][1]);
             if (r0 == r1) {
                 if (r0 != (int)kNoRow) flush(r0, g0 + g1);
             } else {
@@ -511,6 +519,46 @@ struct NextTile {
 };
 
 
+// Window slot of a column j below the tile (j in one of the tile's
+// intervals).  With at most kRegIntervals intervals, their first rows and
+// slot offsets sit in scalar registers (read from the lanes of a NextTile
+// that hold them) and the slot is found by compares, without LDS traffic;
+// otherwise by a binary search over the LDS copy of the interval list.
+constexpr int kRegIntervals = 8;
+typedef int i8v __attribute__((ext_vector_type(8)));
+struct WindowMap {
+    int n;
+    i8v row, off;   // vector types keep the table in registers
+    const int32_t *s_ivrow, *s_ivslot;
+
+    template <class NT>
+    __device__ __forceinline__ void init(const NT &nt, const int32_t *s_iv)
+    {
+        n = nt.NI;
+        s_ivrow = s_iv;
+        s_ivslot = s_iv + nt.NI;
+#pragma unroll
+        for (int k = 0; k < kRegIntervals; ++k) {
+            const int r = __builtin_amdgcn_readlane(nt.ivrow, k);
+            const int sl = __builtin_amdgcn_readlane(nt.ivslot, k);
+            row[k] = k < n ? r : 0x7FFFFFFF;
+            off[k] = k < n ? sl - r : 0;
+        }
+    }
+
+    __device__ __forceinline__ int slot(int j) const
+    {
+        if (n <= kRegIntervals) {
+            int o = off[0];
+#pragma unroll
+            for (int k = 1; k < kRegIntervals; ++k) o = j >= row[k] ? off[k] : o;
+            return j + o;
+        }
+        const int k = upper_index(s_ivrow, n, j);
+        return s_ivslot[k] + (j - s_ivrow[k]);
+    }
+};
+
 // Local buffers of Sec. 3.1 kept in LDS: a tile of rows [r0, r1) accumulates
 // its own rows (s_y) and its effective range below r0 (s_w, compact window
 // slots).  x of both ranges is staged in LDS first (s_x, s_xw).  Own rows go
@@ -527,10 +575,12 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
 {
     using A = typename VT::A;
     extern __shared__ __align__(16) unsigned char lds[];
+    // x of own rows then window slots; sums of own rows then window slots:
+    // an entry's target is one index into both
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_y = s_x + tmax;
-    A *s_xw = s_y + tmax;
-    A *s_w = s_xw + wmax;
+    A *s_xw = s_x + tmax;
+    A *s_y = s_xw + wmax;
+    A *s_w = s_y + tmax;
     uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + 2 * wmax) * sizeof(A)));
     int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                                    align16(((int64_t)emax + 4) * 2));
@@ -544,22 +594,18 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     first.load(nt.kb + 2 * tid, E);
     nt.window(x);
     nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
-    const int r0 = nt.r0, T = nt.T, e0 = nt.e0, NI = nt.NI, W = nt.W;
-    const int32_t *s_ivslot = s_ivrow + NI;
+    const int r0 = nt.r0, T = nt.T, e0 = nt.e0, W = nt.W;
+    WindowMap wm;
+    wm.init(nt, s_ivrow);
     __syncthreads();
     settle_loads();
 
     own_stream<VT, true, true>(
         first, E, s_rid, s_x, [](int) { return true; },
-        [&](int j, A w) -> A {
-            if (j >= r0) {
-                atomic_add(&s_y[j - r0], w);
-                return s_x[j - r0];
-            }
-            const int k = upper_index(s_ivrow, NI, j);
-            const int sl = s_ivslot[k] + (j - s_ivrow[k]);
-            atomic_add(&s_w[sl], w);
-            return s_xw[sl];
+        [&, wm](int j, A w) -> A {
+            const int idx = j >= r0 ? j - r0 : tmax + wm.slot(j);
+            atomic_add(&s_y[idx], w);
+            return s_x[idx];
         },
         [&](int r, A v) { atomic_add(&s_y[r], v); });
     __syncthreads();
@@ -605,9 +651,9 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
     auto buffers = [&](int c, A *&s_x, A *&s_y, A *&s_xw, A *&s_w, uint16_t *&s_rid, int32_t *&s_iv) {
         unsigned char *b = lds + (size_t)c * buf_bytes;
         s_x = reinterpret_cast<A *>(b);
-        s_y = s_x + tmax;
-        s_xw = s_y + tmax;
-        s_w = s_xw + wmax;
+        s_xw = s_x + tmax;
+        s_y = s_xw + wmax;
+        s_w = s_y + tmax;
         s_rid = reinterpret_cast<uint16_t *>(b + align16((2 * (int64_t)tmax + 2 * wmax) * sizeof(A)));
         s_iv = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                            align16(((int64_t)emax + 4) * 2));
@@ -630,13 +676,14 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
     for (int c = 0;; c ^= 1) {
         settle_loads();
         // the tile about to stream
-        const int r0 = nt.r0, T = nt.T, e0 = nt.e0, NI = nt.NI, W = nt.W;
+        const int r0 = nt.r0, T = nt.T, e0 = nt.e0, W = nt.W;
         const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
         A *s_x, *s_y, *s_xw, *s_w;
         uint16_t *s_rid;
         int32_t *s_ivrow;
         buffers(c, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
-        const int32_t *s_ivslot = s_ivrow + NI;
+        WindowMap wm;
+        wm.init(nt, s_ivrow);
 
         const int tn = t + nslot;
         const bool more = tn < hi;
@@ -647,15 +694,10 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
         }
         own_stream<VT, true, true>(
             cur, E, s_rid, s_x, [](int) { return true; },
-            [&](int j, A w) -> A {
-                if (j >= r0) {
-                    atomic_add(&s_y[j - r0], w);
-                    return s_x[j - r0];
-                }
-                const int k = upper_index(s_ivrow, NI, j);
-                const int sl = s_ivslot[k] + (j - s_ivrow[k]);
-                atomic_add(&s_w[sl], w);
-                return s_xw[sl];
+            [&, wm](int j, A w) -> A {
+                const int idx = j >= r0 ? j - r0 : tmax + wm.slot(j);
+                atomic_add(&s_y[idx], w);
+                return s_x[idx];
             },
             [&](int r, A v) { atomic_add(&s_y[r], v); },
             [&]() {
@@ -682,29 +724,42 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
     }
 }
 
-// Merge pass: y_i += partial slots covering i, in ascending tile order.
-// MT is the merge type; COMP adds a TwoSum (Knuth) error term.
+// Merge pass: y_i += the partial slots covering row i, in ascending tile
+// order.  Merge block b (one workgroup, one row per thread) lists segments
+// [lo, hi) with partial index base + i; segments are taken four at a time so
+// their partial loads are in flight together.  MT is the merge type; COMP
+// adds a TwoSum (Knuth) error term.
 template <class A, class YT, class MT, bool COMP>
 __global__ __launch_bounds__(kMergeBlock) void k_merge(int32_t n, PlanDev P, YT *__restrict__ y)
 {
+    constexpr int K = 4;
     const int b = blockIdx.x;
     const int e0 = P.mb_ptr[b], e1 = P.mb_ptr[b + 1];
     const int i = b * kMergeBlock + threadIdx.x;
     if (e0 == e1 || i >= n) return;
     const A *part = reinterpret_cast<const A *>(P.partials);
     MT s = (MT)y[i], c = MT(0);
-    for (int e = e0; e < e1; ++e) {
-        const int g = P.mb_iv[e];
-        const int a = P.iv_row[g], L = P.iv_len[g];
-        if (i >= a && i < a + L) {
-            const MT v = (MT)part[P.iv_goff[g] + (i - a)];
+    for (int e = e0; e < e1; e += K) {
+        A v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] = A(0);
+            if (e + k < e1) {
+                const MergeSeg g = P.mb_seg[e + k];
+                if (i >= g.lo && i < g.hi) v[k] = part[g.base + i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (e + k >= e1) break;
+            const MT w = (MT)v[k];
             if (COMP) {
-                const MT s2 = s + v;
+                const MT s2 = s + w;
                 const MT bp = s2 - s;
-                c += (s - (s2 - bp)) + (v - bp);
+                c += (s - (s2 - bp)) + (w - bp);
                 s = s2;
             } else {
-                s += v;
+                s += w;
             }
         }
     }
@@ -948,11 +1003,10 @@ __device__ __forceinline__ void merge_block_mm(int32_t n, const PlanDev &P, YT *
         const int i = b * kMergeBlock + e / r, c = e % r;
         if (i >= n) break;
         MT s = (MT)Y[(int64_t)i * ldy + c], cm = MT(0);
-        for (int g_ = e0; g_ < e1; ++g_) {
-            const int g = P.mb_iv[g_];
-            const int a = P.iv_row[g], L = P.iv_len[g];
-            if (i >= a && i < a + L) {
-                const MT v = (MT)part[(P.iv_goff[g] + (i - a)) * r + c];
+        for (int e = e0; e < e1; ++e) {
+            const MergeSeg g = P.mb_seg[e];
+            if (i >= g.lo && i < g.hi) {
+                const MT v = (MT)part[(g.base + i) * r + c];
                 if (COMP) {
                     const MT s2 = s + v;
                     const MT bp = s2 - s;
@@ -1165,7 +1219,7 @@ PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials)
     d.iv_slot = (const int32_t *)at(p->t_iv_slot);
     d.iv_goff = (const int64_t *)at(p->t_iv_goff);
     d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
-    d.mb_iv = (const int32_t *)at(p->t_mb_iv);
+    d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
     d.crow = (const int32_t *)at(p->t_crow);
     d.cptr = nullptr;
     d.partials = partials;
@@ -1185,7 +1239,7 @@ static PlanDev plan_dev(const csrc_plan *p, void *ws)
     d.iv_slot = (const int32_t *)at(p->t_iv_slot);
     d.iv_goff = (const int64_t *)at(p->t_iv_goff);
     d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
-    d.mb_iv = (const int32_t *)at(p->t_mb_iv);
+    d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
     d.crow = (const int32_t *)at(p->t_crow);
     d.cptr = nullptr;
     d.partials = b ? b + p->t_partials.offset : nullptr;

@@ -62,6 +62,13 @@ struct Table {
 };
 
 // Device-side view of a single-matrix plan (all pointers into the workspace).
+// A run [lo, hi) of rows of one merge block covered by one window interval;
+// row i's partial is partials[base + i].
+struct MergeSeg {
+    int32_t lo, hi;
+    int64_t base;
+};
+
 struct PlanDev {
     const int32_t *tiles;      // ntiles+1 row boundaries
     const int32_t *tile_k;     // ntiles+1: ia at each boundary (first entry)
@@ -70,8 +77,8 @@ struct PlanDev {
     const int32_t *iv_len;     // rows in each interval
     const int32_t *iv_slot;    // slot of the interval's first row in its tile window
     const int64_t *iv_goff;    // global partial offset of the interval's first row
-    const int32_t *mb_ptr;     // merge blocks: intervals touching each block
-    const int32_t *mb_iv;
+    const int32_t *mb_ptr;     // merge blocks: segments of each block
+    const MergeSeg *mb_seg;
     const int32_t *crow;       // rows sorted by colour
     const int32_t *cptr;       // colour class boundaries (host copy used for launches)
     void *partials;            // partial buffer (PRIVATE)
@@ -116,12 +123,13 @@ struct csrc_plan {
     int32_t ncolors = 0;
     int32_t nmerge_blocks = 0;
     // host tables
-    std::vector<int32_t> tiles, tile_k, iv_ptr, iv_row, iv_len, iv_slot, mb_ptr, mb_iv;
+    std::vector<int32_t> tiles, tile_k, iv_ptr, iv_row, iv_len, iv_slot, mb_ptr;
+    std::vector<csrc::MergeSeg> mb_seg;
     std::vector<int64_t> iv_goff;
     std::vector<int32_t> color, crow, cptr;
     // layout of the workspace
     csrc::Table t_tiles, t_tile_k, t_iv_ptr, t_iv_row, t_iv_len, t_iv_slot, t_iv_goff,
-        t_mb_ptr, t_mb_iv, t_crow, t_partials;
+        t_mb_ptr, t_mb_seg, t_crow, t_partials;
     int64_t blob_bytes = 0;      // bytes of uploaded tables (prefix of workspace)
     int64_t ws_bytes = 0;
     std::vector<char> blob;      // host image of the uploaded tables
