@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -195,9 +197,28 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 slots += w;
                 p->iv_ptr[t + 1] = (int32_t)p->iv_row.size();
                 p->max_window = std::max(p->max_window, w);
+                p->max_span = std::max(p->max_span, p->tiles[t + 1] - p->tiles[t] + w);
                 p->max_intervals = std::max(p->max_intervals, (int32_t)iv.size());
             }
             p->window_slots = slots;
+            p->trec.resize(p->ntiles);
+            for (int32_t t = 0; t < p->ntiles; ++t) {
+                csrc::TileRec r{};
+                r.r0 = p->tiles[t];
+                r.r1 = p->tiles[t + 1];
+                r.k0 = p->tile_k[t];
+                r.k1 = p->tile_k[t + 1];
+                r.e0 = p->iv_ptr[t];
+                r.ni = p->iv_ptr[t + 1] - p->iv_ptr[t];
+                r.w = r.ni ? p->iv_slot[r.e0 + r.ni - 1] + p->iv_len[r.e0 + r.ni - 1] : 0;
+                r.goff = r.ni ? p->iv_goff[r.e0] : 0;
+                for (int k = 0; k < csrc::kRecIntervals; ++k) {
+                    const bool in = k < r.ni;
+                    r.ivrow[k] = in ? p->iv_row[r.e0 + k] : INT32_MAX;
+                    r.ivslot[k] = in ? p->iv_slot[r.e0 + k] : INT32_MAX;
+                }
+                p->trec[t] = r;
+            }
             // merge lists: for each block of kMergeBlock rows, the runs of
             // its rows covered by each interval, in ascending interval (=
             // tile) order
@@ -225,8 +246,7 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                     p->mb_seg[fill[b]++] = sg;
                 }
             }
-            p->lds_bytes = csrc::lds_private(p->max_tile_rows, p->max_window, p->max_tile_entries,
-                                             p->max_intervals, acc);
+            p->lds_bytes = csrc::lds_private(p->max_span, p->max_tile_entries, p->max_intervals, acc);
             if (p->o.persistent) {
                 // two staging buffers
                 p->lds_bytes = 2 * csrc::align16(p->lds_bytes);
@@ -312,6 +332,7 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         put(blob, p->t_iv_goff, p->iv_goff);
         put(blob, p->t_mb_ptr, p->mb_ptr);
         put(blob, p->t_mb_seg, p->mb_seg);
+        put(blob, p->t_trec, p->trec);
         put(blob, p->t_crow, p->crow);
         p->blob_bytes = (int64_t)blob.size();
         p->t_partials.offset = p->blob_bytes;

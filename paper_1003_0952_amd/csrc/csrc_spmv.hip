@@ -397,36 +397,46 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
 // threadIdx.x + s * blockDim.x, s < S).  Every load whose address is known is
 // issued at once, so a tile costs one dependent round trip (intervals, then
 // window x) instead of one per staging step.
+constexpr int kRegIntervals = kRecIntervals;
+typedef int i8v __attribute__((ext_vector_type(8)));
+static_assert(kRegIntervals == 8, "i8v holds the record intervals");
+
 template <class VT, int S>
 struct NextTile {
     using A = typename VT::A;
     int r0, T, k0, k1, kb, e0, NI, W;
+    int64_t goff;
+    i8v rrow, rslot;          // the record's first intervals (uniform)
     A xr[S], dr[S];
     int q0[S], q1[S];
-    int ivrow, ivslot, ivend;
+    int ivrow, ivslot;        // lane l: interval l, when there are more than kRegIntervals
     A xw[S];
 
-    // Issue every load of tile t whose address is known without waiting
-    // (intervals first: the window gather waits for them alone).
+    // Read the tile record (scalar loads) and issue every load whose
+    // address it gives.  Tiles with more than kRegIntervals intervals also
+    // load the interval list, one interval per lane.
     __device__ __forceinline__ void issue(const PlanDev &P, int t, const int32_t *__restrict__ ia,
                                           const typename VT::V *__restrict__ ad,
                                           const typename VT::X *__restrict__ x)
     {
         const int tid = threadIdx.x, lane = tid & 63, B = blockDim.x;
-        r0 = P.tiles[t];
-        T = P.tiles[t + 1] - r0;
-        k0 = P.tile_k[t];
-        k1 = P.tile_k[t + 1];
+        const TileRec *R = P.trec + t;
+        r0 = R->r0;
+        T = R->r1 - r0;
+        k0 = R->k0;
+        k1 = R->k1;
         kb = k0 & ~1;
-        e0 = P.iv_ptr[t];
-        NI = P.iv_ptr[t + 1] - e0;
+        e0 = R->e0;
+        NI = R->ni;
+        W = R->w;
+        goff = R->goff;
+        rrow = *reinterpret_cast<const i8v *>(R->ivrow);
+        rslot = *reinterpret_cast<const i8v *>(R->ivslot);
         ivrow = 0;
         ivslot = 0x7FFFFFFF;
-        ivend = 0;
-        if (lane < NI) {
+        if (NI > kRegIntervals && lane < NI) {
             ivrow = P.iv_row[e0 + lane];
             ivslot = P.iv_slot[e0 + lane];
-            ivend = ivslot + P.iv_len[e0 + lane];
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -441,10 +451,20 @@ struct NextTile {
     }
 
     // Row of window slot sl: the slot lies in the last interval whose first
-    // slot is <= sl, found by a binary search over the lanes (every lane of
-    // the wave takes part).
+    // slot is <= sl, found by compares over the record's intervals, or by a
+    // binary search over the lanes (every lane of the wave takes part).
     __device__ __forceinline__ int window_row(int sl) const
     {
+        if (NI <= kRegIntervals) {
+            int a = rrow[0], b = rslot[0];
+#pragma unroll
+            for (int k = 1; k < kRegIntervals; ++k) {
+                const bool in = sl >= rslot[k];
+                a = in ? rrow[k] : a;
+                b = in ? rslot[k] : b;
+            }
+            return a + (sl - b);
+        }
         int k = 0;
 #pragma unroll
         for (int step = 32; step > 0; step >>= 1) {
@@ -459,8 +479,6 @@ struct NextTile {
     __device__ __forceinline__ void window(const typename VT::X *__restrict__ x)
     {
         const int tid = threadIdx.x, B = blockDim.x;
-        W = __shfl(ivend, NI > 0 ? NI - 1 : 0);
-        if (NI == 0) W = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int sl = tid + s * B;
@@ -495,7 +513,7 @@ struct NextTile {
         const int len = ((k1 - kb) + 3) & ~1;
         for (int q = tid; q < k0 - kb; q += B) s_rid[q] = kNoRow;
         for (int q = (k1 - kb) + tid; q < len; q += B) s_rid[q] = kNoRow;
-        if (tid < NI) {
+        if (NI > kRegIntervals && tid < NI) {
             s_ivrow[tid] = ivrow;
             s_ivrow[NI + tid] = ivslot;
         }
@@ -524,8 +542,6 @@ struct NextTile {
 // slot offsets sit in scalar registers (read from the lanes of a NextTile
 // that hold them) and the slot is found by compares, without LDS traffic;
 // otherwise by a binary search over the LDS copy of the interval list.
-constexpr int kRegIntervals = 8;
-typedef int i8v __attribute__((ext_vector_type(8)));
 struct WindowMap {
     int n;
     i8v row, off;   // vector types keep the table in registers
@@ -537,13 +553,8 @@ struct WindowMap {
         n = nt.NI;
         s_ivrow = s_iv;
         s_ivslot = s_iv + nt.NI;
-#pragma unroll
-        for (int k = 0; k < kRegIntervals; ++k) {
-            const int r = __builtin_amdgcn_readlane(nt.ivrow, k);
-            const int sl = __builtin_amdgcn_readlane(nt.ivslot, k);
-            row[k] = k < n ? r : 0x7FFFFFFF;
-            off[k] = k < n ? sl - r : 0;
-        }
+        row = nt.rrow;
+        off = nt.rslot - nt.rrow;   // unused entries: INT32_MAX rows, never selected
     }
 
     __device__ __forceinline__ int slot(int j) const
@@ -571,17 +582,15 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
                                                  const typename VT::V *__restrict__ al,
                                                  const typename VT::V *__restrict__ au,
                                                  const typename VT::X *__restrict__ x,
-                                                 YT *__restrict__ y, int tmax, int wmax, int emax)
+                                                 YT *__restrict__ y, int smax, int emax)
 {
     using A = typename VT::A;
     extern __shared__ __align__(16) unsigned char lds[];
-    // x of own rows then window slots; sums of own rows then window slots:
-    // an entry's target is one index into both
+    // x of the T own rows then the window slots; sums likewise: an entry's
+    // target is one index into both
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_xw = s_x + tmax;
-    A *s_y = s_xw + wmax;
-    A *s_w = s_y + tmax;
-    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + 2 * wmax) * sizeof(A)));
+    A *s_y = s_x + smax;
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16(2 * (int64_t)smax * sizeof(A)));
     int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                                    align16(((int64_t)emax + 4) * 2));
 
@@ -589,12 +598,14 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     NextTile<VT, 2> nt;
     nt.issue(P, t, ia, ad, x);
+    A *s_xw = s_x + nt.T;
+    A *s_w = s_y + nt.T;
     const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
     Batch<VT, true, true, true> first;
     first.load(nt.kb + 2 * tid, E);
     nt.window(x);
     nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
-    const int r0 = nt.r0, T = nt.T, e0 = nt.e0, W = nt.W;
+    const int r0 = nt.r0, T = nt.T, W = nt.W;
     WindowMap wm;
     wm.init(nt, s_ivrow);
     __syncthreads();
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     own_stream<VT, true, true>(
         first, E, s_rid, s_x, [](int) { return true; },
         [&, wm](int j, A w) -> A {
-            const int idx = j >= r0 ? j - r0 : tmax + wm.slot(j);
+            const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
             atomic_add(&s_y[idx], w);
             return s_x[idx];
         },
@@ -612,7 +623,7 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
 
     for (int i = tid; i < T; i += B) y[r0 + i] = (YT)s_y[i];
     if (W) {
-        A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0];
+        A *part = reinterpret_cast<A *>(P.partials) + nt.goff;
         for (int sl = tid; sl < W; sl += B) part[sl] = s_w[sl];
     }
 }
@@ -635,8 +646,7 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
                                                    const typename VT::V *__restrict__ al,
                                                    const typename VT::V *__restrict__ au,
                                                    const typename VT::X *__restrict__ x,
-                                                   YT *__restrict__ y, int tmax, int wmax, int emax,
-                                                   int buf_bytes)
+                                                   YT *__restrict__ y, int smax, int emax, int buf_bytes)
 {
     using A = typename VT::A;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -648,13 +658,14 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
     int t = (int)((int64_t)xcd * ntiles / X) + slot;
     if (t >= hi) return;
 
-    auto buffers = [&](int c, A *&s_x, A *&s_y, A *&s_xw, A *&s_w, uint16_t *&s_rid, int32_t *&s_iv) {
+    // buffer c for a tile of T rows
+    auto buffers = [&](int c, int T, A *&s_x, A *&s_y, A *&s_xw, A *&s_w, uint16_t *&s_rid, int32_t *&s_iv) {
         unsigned char *b = lds + (size_t)c * buf_bytes;
         s_x = reinterpret_cast<A *>(b);
-        s_xw = s_x + tmax;
-        s_y = s_xw + wmax;
-        s_w = s_y + tmax;
-        s_rid = reinterpret_cast<uint16_t *>(b + align16((2 * (int64_t)tmax + 2 * wmax) * sizeof(A)));
+        s_y = s_x + smax;
+        s_xw = s_x + T;
+        s_w = s_y + T;
+        s_rid = reinterpret_cast<uint16_t *>(b + align16(2 * (int64_t)smax * sizeof(A)));
         s_iv = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                            align16(((int64_t)emax + 4) * 2));
     };
@@ -668,7 +679,7 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
         A *s_x, *s_y, *s_xw, *s_w;
         uint16_t *s_rid;
         int32_t *s_iv;
-        buffers(0, s_x, s_y, s_xw, s_w, s_rid, s_iv);
+        buffers(0, nt.T, s_x, s_y, s_xw, s_w, s_rid, s_iv);
         nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_iv);
     }
     __syncthreads();
@@ -676,12 +687,13 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
     for (int c = 0;; c ^= 1) {
         settle_loads();
         // the tile about to stream
-        const int r0 = nt.r0, T = nt.T, e0 = nt.e0, W = nt.W;
+        const int r0 = nt.r0, T = nt.T, W = nt.W;
+        const int64_t goff = nt.goff;
         const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
         A *s_x, *s_y, *s_xw, *s_w;
         uint16_t *s_rid;
         int32_t *s_ivrow;
-        buffers(c, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
+        buffers(c, T, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
         WindowMap wm;
         wm.init(nt, s_ivrow);
 
@@ -695,7 +707,7 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
         own_stream<VT, true, true>(
             cur, E, s_rid, s_x, [](int) { return true; },
             [&, wm](int j, A w) -> A {
-                const int idx = j >= r0 ? j - r0 : tmax + wm.slot(j);
+                const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
                 atomic_add(&s_y[idx], w);
                 return s_x[idx];
             },
@@ -707,7 +719,7 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
 
         for (int i = tid; i < T; i += 512) y[r0 + i] = (YT)s_y[i];
         if (W) {
-            A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0];
+            A *part = reinterpret_cast<A *>(P.partials) + goff;
             for (int sl = tid; sl < W; sl += 512) part[sl] = s_w[sl];
         }
         if (!more) break;
@@ -715,7 +727,7 @@ __global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int
             A *n_x, *n_y, *n_xw, *n_w;
             uint16_t *n_rid;
             int32_t *n_iv;
-            buffers(c ^ 1, n_x, n_y, n_xw, n_w, n_rid, n_iv);
+            buffers(c ^ 1, nt.T, n_x, n_y, n_xw, n_w, n_rid, n_iv);
             nt.stage(ia, ad, x, n_x, n_y, n_xw, n_w, n_rid, n_iv);
         }
         __syncthreads();
@@ -1220,6 +1232,7 @@ PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials)
     d.iv_goff = (const int64_t *)at(p->t_iv_goff);
     d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
     d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
+    d.trec = (const TileRec *)at(p->t_trec);
     d.crow = (const int32_t *)at(p->t_crow);
     d.cptr = nullptr;
     d.partials = partials;
@@ -1240,6 +1253,7 @@ static PlanDev plan_dev(const csrc_plan *p, void *ws)
     d.iv_goff = (const int64_t *)at(p->t_iv_goff);
     d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
     d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
+    d.trec = (const TileRec *)at(p->t_trec);
     d.crow = (const int32_t *)at(p->t_crow);
     d.cptr = nullptr;
     d.partials = b ? b + p->t_partials.offset : nullptr;
@@ -1289,8 +1303,9 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
     }
     case CSRC_V_PRIVATE: {
         const int tmax = p->max_tile_rows, wmax = p->max_window, emax = p->max_tile_entries;
+        const int smax = p->max_span;
         if (single) {
-            const size_t lds = (size_t)lds_private(tmax, wmax, emax, p->max_intervals, sizeof(Acc));
+            const size_t lds = (size_t)lds_private(smax, emax, p->max_intervals, sizeof(Acc));
             if (p->o.persistent) {
                 if (B != 512 || p->max_intervals > 64 || 2 * align16((int64_t)lds) > kLdsBudget)
                     return CSRC_ERR_UNSUPPORTED;
@@ -1307,12 +1322,12 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
                     grid = std::max(8, device_cus() * per_cu);
                     p->persistent_grid.store(grid, std::memory_order_relaxed);
                 }
-                kern<<<grid, 512, 2 * (size_t)buf, s>>>(P, p->ntiles, A->k, A->ia, A->ja, ad, al, au, x, y, tmax,
-                                                       wmax, emax, buf);
+                kern<<<grid, 512, 2 * (size_t)buf, s>>>(P, p->ntiles, A->k, A->ia, A->ja, ad, al, au, x, y, smax,
+                                                       emax, buf);
             } else {
                 auto kern = k_private<VT, YT>;
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
-                kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, wmax, emax);
+                kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
             }
             if (p->nmerge_blocks > 0 && p->window_slots > 0) {
                 if (std::is_same<YT, double>::value)

@@ -28,13 +28,14 @@ constexpr int kPullEntries = 16384;   // stored entries per pull chunk (OWNER)
 
 // Dynamic LDS of the flat tile kernels (acc = accumulator bytes).  Row ids
 // of a block's entries are uint16, padded by 4.
-//   PRIVATE: x, y of own rows; x, partial of window slots; row ids; window
-//            interval starts and slots
+//   PRIVATE: x of own rows then window slots, sums of own rows then window
+//            slots (each sized by the largest rows + slots of one tile, smax);
+//            row ids; window interval starts and slots
 //   OWNER:   x, y of own rows; x of pulled rows; row ids
 //   ATOMIC:  x, y of own rows; row ids
-inline int64_t lds_private(int64_t tmax, int64_t wmax, int64_t emax, int64_t ivmax, int acc)
+inline int64_t lds_private(int64_t smax, int64_t emax, int64_t ivmax, int acc)
 {
-    return align16((2 * tmax + 2 * wmax) * acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+    return align16(2 * smax * acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
 inline int64_t lds_owner(int64_t tmax, int64_t pmax, int64_t emax, int acc)
 {
@@ -69,6 +70,21 @@ struct MergeSeg {
     int64_t base;
 };
 
+// Per-tile record of a PRIVATE plan, 128 bytes read with scalar loads: the
+// tile's rows [r0, r1) and entries [k0, k1), its window (ni intervals from
+// global interval e0, w slots, partials from goff) and the first
+// kRecIntervals intervals' first row and first slot (unused: INT32_MAX).
+constexpr int kRecIntervals = 8;
+struct TileRec {
+    int32_t r0, r1, k0, k1;
+    int32_t e0, ni, w, pad0;
+    int64_t goff;
+    int32_t pad1[6];
+    int32_t ivrow[kRecIntervals];
+    int32_t ivslot[kRecIntervals];
+};
+static_assert(sizeof(TileRec) == 128, "tile record size");
+
 struct PlanDev {
     const int32_t *tiles;      // ntiles+1 row boundaries
     const int32_t *tile_k;     // ntiles+1: ia at each boundary (first entry)
@@ -77,6 +93,7 @@ struct PlanDev {
     const int32_t *iv_len;     // rows in each interval
     const int32_t *iv_slot;    // slot of the interval's first row in its tile window
     const int64_t *iv_goff;    // global partial offset of the interval's first row
+    const TileRec *trec;       // PRIVATE: per-tile records
     const int32_t *mb_ptr;     // merge blocks: segments of each block
     const MergeSeg *mb_seg;
     const int32_t *crow;       // rows sorted by colour
@@ -112,6 +129,7 @@ struct csrc_plan {
     int32_t ntiles = 0;
     int32_t max_tile_rows = 0;
     int32_t max_window = 0;     // PRIVATE: slots; OWNER: pulled rows
+    int32_t max_span = 0;       // PRIVATE: largest rows + window slots of a tile
     int32_t max_intervals = 0;
     int32_t max_tile_entries = 0;   // stored lower entries of the largest tile
     int32_t max_pull_rows = 0;      // OWNER: rows of the largest pull chunk
@@ -125,11 +143,12 @@ struct csrc_plan {
     // host tables
     std::vector<int32_t> tiles, tile_k, iv_ptr, iv_row, iv_len, iv_slot, mb_ptr;
     std::vector<csrc::MergeSeg> mb_seg;
+    std::vector<csrc::TileRec> trec;
     std::vector<int64_t> iv_goff;
     std::vector<int32_t> color, crow, cptr;
     // layout of the workspace
     csrc::Table t_tiles, t_tile_k, t_iv_ptr, t_iv_row, t_iv_len, t_iv_slot, t_iv_goff,
-        t_mb_ptr, t_mb_seg, t_crow, t_partials;
+        t_mb_ptr, t_mb_seg, t_trec, t_crow, t_partials;
     int64_t blob_bytes = 0;      // bytes of uploaded tables (prefix of workspace)
     int64_t ws_bytes = 0;
     std::vector<char> blob;      // host image of the uploaded tables
