@@ -182,6 +182,14 @@ typedef struct csrc_plan_opts {
     int32_t grid;             /* workgroups of the persistent launch (>= 8, one
                                  tile range per XCD); 0 = as many as fit on
                                  the device at once                           */
+    int32_t atomic_merge;     /* PRIVATE, one right-hand side, not persistent:
+                                 1 = y is cleared and every tile adds its own
+                                 rows and its window sums to y with global
+                                 atomics (no partial buffer, no merge pass;
+                                 the order of the additions, hence the
+                                 rounding, varies from run to run); 0 = window
+                                 sums go to the partial buffer and a second
+                                 pass adds them in tile order (deterministic) */
 } csrc_plan_opts;
 
 /* Fills opts with the defaults of a variant. */

@@ -127,7 +127,7 @@ class Plan:
 
     def __init__(self, A, variant="private", tile_work=0, lanes=0, block=0,
                  color_criterion=B.COLOR_WRITE_SET, ydtype="f32", compensated=False,
-                 max_rhs=1, persistent=0, grid=0, stream=None):
+                 max_rhs=1, persistent=0, grid=0, atomic_merge=0, stream=None):
         import torch
         self.variant = _variant(variant)
         opts = B.PlanOpts()
@@ -141,6 +141,7 @@ class Plan:
         opts.max_rhs = int(max_rhs)
         opts.persistent = int(persistent)
         opts.grid = int(grid)
+        opts.atomic_merge = int(atomic_merge)
         h = ctypes.c_void_p(0)
         check(B.lib.csrc_plan_create(A.n, np_ptr(A.host_ia), np_ptr(A.host_ja), A.vdtype,
                                      ctypes.byref(opts), ctypes.byref(h)), "csrc_plan_create")

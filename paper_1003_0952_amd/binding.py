@@ -82,7 +82,8 @@ class CsrcMatrix(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("variant", I32), ("tile_work", I32), ("lanes", I32), ("block", I32),
                 ("color_criterion", I32), ("ydtype", I32), ("compensated", I32),
-                ("max_rhs", I32), ("persistent", I32), ("grid", I32)]
+                ("max_rhs", I32), ("persistent", I32), ("grid", I32),
+                ("atomic_merge", I32)]
 
 
 class PlanInfo(ctypes.Structure):

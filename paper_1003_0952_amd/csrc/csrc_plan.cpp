@@ -124,6 +124,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
     if (o.tile_work < 0 || o.max_rhs < 0 || o.max_rhs > csrc::kMaxRhs) return CSRC_ERR_ARG;
     if (o.persistent < 0 || o.persistent > 1 || o.grid < 0 || (o.grid > 0 && o.grid < 8)) return CSRC_ERR_ARG;
     if (o.persistent && (o.variant != CSRC_V_PRIVATE || (o.block != 0 && o.block != 512))) return CSRC_ERR_ARG;
+    if (o.atomic_merge < 0 || o.atomic_merge > 1) return CSRC_ERR_ARG;
+    if (o.atomic_merge && (o.variant != CSRC_V_PRIVATE || o.persistent || o.compensated)) return CSRC_ERR_ARG;
     if (vdtype != CSRC_F64 && o.ydtype != CSRC_F32 && o.ydtype != CSRC_F64) return CSRC_ERR_ARG;
     *out = nullptr;
     csrc_plan *p = nullptr;
@@ -248,8 +250,18 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             }
             p->lds_bytes = csrc::lds_private(p->max_span, p->max_tile_entries, p->max_intervals, acc);
             if (p->o.persistent) {
-                // two staging buffers
-                p->lds_bytes = 2 * csrc::align16(p->lds_bytes);
+                // two staging buffers, rows and window intervals padded to
+                // 16-byte chunks; every tile's intervals fit its record
+                if (p->max_intervals > csrc::kRecIntervals) { delete p; return CSRC_ERR_UNSUPPORTED; }
+                const int32_t e = 16 / acc;
+                auto pad = [&](int32_t v) { return (v + e - 1) / e * e; };
+                for (const csrc::TileRec &r : p->trec) {
+                    int32_t sp = pad(r.r1 - r.r0);
+                    for (int k = 0; k < r.ni; ++k)
+                        sp += pad((k + 1 < r.ni ? r.ivslot[k + 1] : r.w) - r.ivslot[k]);
+                    p->max_span_padded = std::max(p->max_span_padded, sp);
+                }
+                p->lds_bytes = 2 * csrc::align16(csrc::lds_private_padded(p->max_span_padded, p->max_tile_entries, acc));
             }
             if (p->o.max_rhs > 1)
                 p->lds_bytes = std::max(p->lds_bytes,
@@ -336,7 +348,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         put(blob, p->t_crow, p->crow);
         p->blob_bytes = (int64_t)blob.size();
         p->t_partials.offset = p->blob_bytes;
-        p->t_partials.bytes = p->window_slots * acc * p->o.max_rhs;
+        // the atomic merge of single products needs no partials
+        p->t_partials.bytes = (p->o.atomic_merge && p->o.max_rhs == 1) ? 0 : p->window_slots * acc * p->o.max_rhs;
         p->ws_bytes = csrc::align256(p->blob_bytes + p->t_partials.bytes);
         if (v == CSRC_V_PLAIN) p->ws_bytes = 0;
         *out = p;

@@ -270,12 +270,68 @@ __device__ __forceinline__ void settle_loads() { __builtin_amdgcn_s_waitcnt(0); 
 // them).  The batch loop runs the same number of times in every lane (lanes
 // past k1 see only kNoRow), so after_first() is called once, by all lanes
 // together, after the first batch.
+// Process one batch held in cur (lane pairs at qb and qb + 2B of the
+// entries E): for each entry of row r (relative) with column j,
+// x_j = ent(j, au * s_x[r]) scatters and gathers, and a lane's run of
+// gathered products of one row goes to flush(r, sum).  With LOAD_AU false,
+// an au pair is fetched only if need_au(j) holds for one of its entries
+// (else its products are zero and ent ignores them).
+template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush>
+__device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT> &cur, int qb, const Entries<VT, NT> &E,
+                                              const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
+                                              NeedAu need_au, Ent ent, Flush flush)
+{
+    using A = typename VT::A;
+    const int half = 2 * (int)blockDim.x;
+    const int kb = E.kb, k1 = E.ke;
+    uint32_t rv[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int q = qb + half * s;
+        rv[s] = q < k1 ? *reinterpret_cast<const uint32_t *>(s_rid + (q - kb)) : 0xFFFFFFFFu;
+    }
+    if (!LOAD_AU) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool need = ((rv[s] & 0xFFFF) != kNoRow && need_au(cur.j[s][0])) ||
+                              ((rv[s] >> 16) != kNoRow && need_au(cur.j[s][1]));
+            if (need) E.au2(qb + half * s, cur.u[s]);
+            else cur.u[s][0] = cur.u[s][1] = A(0);
+        }
+    }
+    // x of the entries' own rows, read before any LDS update of the batch
+    A xr[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
+        xr[s][0] = s_x[r0 != (int)kNoRow ? r0 : 0];
+        xr[s][1] = s_x[r1 != (int)kNoRow ? r1 : 0];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
+        A g0 = A(0), g1 = A(0);
+        if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * xr[s][0]);
+        if (r1 != (int)kNoRow) g1 = cur.a[s][1] * ent(cur.j[s][1], cur.u[s][1] * xr[s][1]);
+        if (r0 == r1) {
+            if (r0 != (int)kNoRow) flush(r0, g0 + g1);
+        } else {
+            if (r0 != (int)kNoRow) flush(r0, g0);
+            if (r1 != (int)kNoRow) flush(r1, g1);
+        }
+    }
+}
+
+// Stream entries [kb, k1) of E (kb = k0 rounded down to even).  `cur` holds
+// the first batch, issued by the caller before its staging; each batch is
+// processed while the next one loads.  The batch loop runs the same number
+// of times in every lane (lanes past k1 see only kNoRow), so after_first()
+// is called once, by all lanes together, after the first batch.
 template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush, class Hook = NoHook>
 __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, const Entries<VT, NT> &E,
                                            const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
                                            NeedAu need_au, Ent ent, Flush flush, Hook after_first = Hook())
 {
-    using A = typename VT::A;
     const int half = 2 * (int)blockDim.x;
     const int kb = E.kb, k1 = E.ke;
     int base = kb;
@@ -283,42 +339,7 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, co
         const int qb = base + 2 * (int)threadIdx.x;
         Batch<VT, true, LOAD_AU, NT> nxt;
         if (base + 2 * half < k1) nxt.load(qb + 2 * half, E);
-        uint32_t rv[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int q = qb + half * s;
-            rv[s] = q < k1 ? *reinterpret_cast<const uint32_t *>(s_rid + (q - kb)) : 0xFFFFFFFFu;
-        }
-        if (!LOAD_AU) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const bool need = ((rv[s] & 0xFFFF) != kNoRow && need_au(cur.j[s][0])) ||
-                                  ((rv[s] >> 16) != kNoRow && need_au(cur.j[s][1]));
-                if (need) E.au2(qb + half * s, cur.u[s]);
-                else cur.u[s][0] = cur.u[s][1] = A(0);
-            }
-        }
-        // x of the entries' own rows, read before any LDS update of the batch
-        A xr[2][2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
-            xr[s][0] = s_x[r0 != (int)kNoRow ? r0 : 0];
-            xr[s][1] = s_x[r1 != (int)kNoRow ? r1 : 0];
-        }
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
-            A g0 = A(0), g1 = A(0);
-            if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * xr[s][0]);
-            if (r1 != (int)kNoRow) g1 = cur.a[s][1] * ent(cur.j[s][1], cur.u[s][1] * xr[s][1]);
-            if (r0 == r1) {
-                if (r0 != (int)kNoRow) flush(r0, g0 + g1);
-            } else {
-                if (r0 != (int)kNoRow) flush(r0, g0);
-                if (r1 != (int)kNoRow) flush(r1, g1);
-            }
-        }
+        process_batch<VT, LOAD_AU, NT>(cur, qb, E, s_rid, s_x, need_au, ent, flush);
         if (base == kb) after_first();
         cur = nxt;
         base += 2 * half;
@@ -575,7 +596,9 @@ struct WindowMap {
 // slots).  x of both ranges is staged in LDS first (s_x, s_xw).  Own rows go
 // to y; window slots go to the partial buffer for the merge pass.  All
 // staging loads and the first batch of entries are in flight together.
-template <class VT, class YT>
+// AM (atomic merge): y is zero beforehand and both the own rows and the
+// window slots are added to y with global atomics; no partials, no pass.
+template <class VT, class YT, bool AM>
 __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
                                                  const typename VT::V *__restrict__ ad,
@@ -621,6 +644,15 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
         [&](int r, A v) { atomic_add(&s_y[r], v); });
     __syncthreads();
 
+    if (AM) {
+        for (int i = tid; i < T; i += B) atomic_add(&y[r0 + i], (YT)s_y[i]);
+        for (int base = 0; base < W; base += B) {
+            const int sl = base + tid;
+            const int row = nt.window_row(sl);   // every lane takes part
+            if (sl < W) atomic_add(&y[row], (YT)s_w[sl]);
+        }
+        return;
+    }
     for (int i = tid; i < T; i += B) y[r0 + i] = (YT)s_y[i];
     if (W) {
         A *part = reinterpret_cast<A *>(P.partials) + nt.goff;
@@ -630,109 +662,253 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
 
 // ----------------------------------------------------- PRIVATE, persistent
 
-// PRIVATE with persistent workgroups (512 threads).  XCD x (workgroups
-// b = x mod 8) owns the contiguous tile range [x ntiles / 8, (x+1) ntiles / 8)
-// and its workgroups take those tiles in turn.  Two LDS buffers alternate:
-// while tile t streams out of one, the loads of tile t+1 (rows, intervals,
-// window x and its first batch) are in flight, and tile t+1 is written into
-// the other buffer as soon as t's stream ends, so the memory pipe does not
-// drain between tiles.  Per tile the arithmetic is that of k_private.
-// Each thread prefetches S rows and S window slots of the next tile.
-template <class VT, class YT, int S>
-__global__ __launch_bounds__(512, 4) void k_private_p(PlanDev P, int ntiles, int64_t kend,
-                                                   const int32_t *__restrict__ ia,
-                                                   const int32_t *__restrict__ ja,
-                                                   const typename VT::V *__restrict__ ad,
-                                                   const typename VT::V *__restrict__ al,
-                                                   const typename VT::V *__restrict__ au,
-                                                   const typename VT::X *__restrict__ x,
-                                                   YT *__restrict__ y, int smax, int emax, int buf_bytes)
+// PRIVATE with persistent workgroups.  XCD x (workgroups b = x mod 8) owns
+// the tile range [x ntiles / 8, (x+1) ntiles / 8), split into contiguous runs,
+// one per workgroup of that XCD.  A workgroup streams its run tile after
+// tile; two LDS buffers alternate.  While tile t streams out of one buffer:
+//   * the x values of tile t+1 (own rows, then each window interval padded
+//     to whole 16-byte chunks) are copied into the other buffer by LDS-direct
+//     buffer loads, which hold no registers;
+//   * its diagonal and row starts (row threadIdx.x) are loaded to registers;
+//   * its first batch of entries is loaded by the last batch step of tile t
+//     (two register batches alternate, so no copy forces an early wait).
+// At the switch every wave waits for its own copies but not for the batch in
+// flight, then the workgroup writes tile t out and sets tile t+1 up (sums,
+// row ids).  Per tile the arithmetic is that of k_private.
+constexpr int kPersistentBlock = 512;
+
+__device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t r, uint32_t off, void *lds_base)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds_base, 16, off, 0, 0,
+                                             0);
+}
+
+// Wait until at most n vector memory operations are outstanding (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left at maximum).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Vector memory operations of one Batch::load of all three arrays.
+template <class VT> struct BatchLoads { static constexpr int N = 6; };
+template <> struct BatchLoads<B16T> { static constexpr int N = 10; };
+
+// A tile of the persistent kernel: its record plus the LDS layout of its x
+// values: own rows at [0, T), window interval k at pos[k], each region padded
+// to a multiple of E values (one 16-byte chunk); span = end of the last one.
+template <int E>
+struct PTile {
+    int r0, T, k0, k1, kb, NI, W, span;
+    int64_t goff;
+    i8v row, slot, pos;
+
+    __device__ __forceinline__ void read(const PlanDev &P, int t)
+    {
+        const TileRec *R = P.trec + t;
+        r0 = R->r0;
+        T = R->r1 - r0;
+        k0 = R->k0;
+        k1 = R->k1;
+        kb = k0 & ~1;
+        NI = R->ni;
+        W = R->w;
+        goff = R->goff;
+        row = *reinterpret_cast<const i8v *>(R->ivrow);
+        slot = *reinterpret_cast<const i8v *>(R->ivslot);
+        int p = (T + E - 1) & ~(E - 1);
+#pragma unroll
+        for (int k = 0; k < kRegIntervals; ++k) {
+            pos[k] = p;
+            if (k < NI) {
+                const int end = k + 1 < NI ? slot[k + 1] : W;
+                p += (end - slot[k] + E - 1) & ~(E - 1);
+            }
+        }
+        span = p;
+    }
+
+    // LDS index of compact window slot sl
+    __device__ __forceinline__ int slot_index(int sl) const
+    {
+        int o = pos[0] - slot[0];
+#pragma unroll
+        for (int k = 1; k < kRegIntervals; ++k) o = sl >= slot[k] ? pos[k] - slot[k] : o;
+        return sl + o;
+    }
+    // LDS index of window column j
+    __device__ __forceinline__ int col_index(int j) const
+    {
+        int o = pos[0] - row[0];
+#pragma unroll
+        for (int k = 1; k < kRegIntervals; ++k) o = j >= row[k] ? pos[k] - row[k] : o;
+        return j + o;
+    }
+};
+
+template <class VT, class YT>
+__global__ __launch_bounds__(kPersistentBlock) void k_private_p(PlanDev P, int ntiles, int32_t n,
+                                                                const int32_t *__restrict__ ia,
+                                                                const int32_t *__restrict__ ja,
+                                                                const typename VT::V *__restrict__ ad,
+                                                                const typename VT::V *__restrict__ al,
+                                                                const typename VT::V *__restrict__ au,
+                                                                const typename VT::X *__restrict__ x,
+                                                                YT *__restrict__ y, int smax, int emax,
+                                                                int buf_bytes)
 {
     using A = typename VT::A;
+    static_assert(sizeof(A) == sizeof(typename VT::X), "x is copied into LDS as is");
+    constexpr int E = 16 / sizeof(A);
+    constexpr int B = kPersistentBlock;
     extern __shared__ __align__(16) unsigned char lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = B / 64;
+
+    // this workgroup's run of tiles
     constexpr int X = 8;
-    const int tid = threadIdx.x;
     const int xcd = blockIdx.x % X, slot = blockIdx.x / X;
     const int nslot = ((int)gridDim.x - xcd + X - 1) / X;
-    const int hi = (int)((int64_t)(xcd + 1) * ntiles / X);
-    int t = (int)((int64_t)xcd * ntiles / X) + slot;
-    if (t >= hi) return;
+    const int lo = (int)((int64_t)xcd * ntiles / X), hi = (int)((int64_t)(xcd + 1) * ntiles / X);
+    const int ta = lo + (int)((int64_t)(hi - lo) * slot / nslot);
+    const int tb = lo + (int)((int64_t)(hi - lo) * (slot + 1) / nslot);
+    if (ta >= tb) return;
 
-    // buffer c for a tile of T rows
-    auto buffers = [&](int c, int T, A *&s_x, A *&s_y, A *&s_xw, A *&s_w, uint16_t *&s_rid, int32_t *&s_iv) {
-        unsigned char *b = lds + (size_t)c * buf_bytes;
-        s_x = reinterpret_cast<A *>(b);
-        s_y = s_x + smax;
-        s_xw = s_x + T;
-        s_w = s_y + T;
-        s_rid = reinterpret_cast<uint16_t *>(b + align16(2 * (int64_t)smax * sizeof(A)));
-        s_iv = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
-                                           align16(((int64_t)emax + 4) * 2));
+    auto bx = [&](int c) { return reinterpret_cast<A *>(lds + (size_t)c * buf_bytes); };
+    auto by = [&](int c) { return bx(c) + smax; };
+    auto brid = [&](int c) {
+        return reinterpret_cast<uint16_t *>(lds + (size_t)c * buf_bytes + align16(2 * (int64_t)smax * sizeof(A)));
+    };
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(x, (uint32_t)n * (uint32_t)sizeof(A));
+
+    // registers of the tile being staged: diagonal and row start of row tid
+    A nad = A(0);
+    int nq0 = 0, nq1 = 0;
+
+    // start tile u's staging into buffer c
+    auto stage_issue = [&](const PTile<E> &u, int c) {
+        A *sx = bx(c);
+        const int nco = (u.T + E - 1) / E;
+        for (int cb = wave * 64; cb < nco; cb += NW * 64) {
+            const int ch = cb + lane;
+            if (ch < nco) lds_copy16(rx, (uint32_t)(u.r0 + ch * E) * (uint32_t)sizeof(A), sx + cb * E);
+        }
+        const int w0 = u.pos[0], ncw = (u.span - w0) / E;
+        for (int cb = wave * 64; cb < ncw; cb += NW * 64) {
+            const int ch = cb + lane;
+            const int e = w0 + ch * E;    // LDS index of the chunk
+            int o = u.row[0] - u.pos[0];
+#pragma unroll
+            for (int k = 1; k < kRegIntervals; ++k) o = e >= u.pos[k] ? u.row[k] - u.pos[k] : o;
+            if (ch < ncw) lds_copy16(rx, (uint32_t)(e + o) * (uint32_t)sizeof(A), sx + w0 + cb * E);
+        }
+        if (tid < u.T) {
+            nad = (A)ldv(ad, u.r0 + tid);
+            nq0 = ia[u.r0 + tid];
+            nq1 = ia[u.r0 + tid + 1];
+        }
+    };
+    // tile u's sums and row ids in buffer c (its x values have landed)
+    auto stage_finish = [&](const PTile<E> &u, int c) {
+        const A *sx = bx(c);
+        A *sy = by(c);
+        uint16_t *rid = brid(c);
+        if (tid < u.T) {
+            sy[tid] = nad * sx[tid];
+            for (int q = nq0; q < nq1; ++q) rid[q - u.kb] = (uint16_t)tid;
+        }
+        for (int i = tid + B; i < u.T; i += B) {
+            sy[i] = (A)ldv(ad, u.r0 + i) * sx[i];
+            const int q1 = ia[u.r0 + i + 1];
+            for (int q = ia[u.r0 + i]; q < q1; ++q) rid[q - u.kb] = (uint16_t)i;
+        }
+        for (int i = u.T + tid; i < u.span; i += B) sy[i] = A(0);
+        const int len = ((u.k1 - u.kb) + 3) & ~1;
+        for (int q = tid; q < u.k0 - u.kb; q += B) rid[q] = kNoRow;
+        for (int q = (u.k1 - u.kb) + tid; q < len; q += B) rid[q] = kNoRow;
+    };
+    auto write_out = [&](const PTile<E> &u, int c) {
+        const A *sy = by(c);
+        for (int i = tid; i < u.T; i += B) y[u.r0 + i] = (YT)sy[i];
+        if (u.W) {
+            A *part = reinterpret_cast<A *>(P.partials) + u.goff;
+            for (int sl = tid; sl < u.W; sl += B) part[sl] = sy[u.slot_index(sl)];
+        }
     };
 
-    NextTile<VT, S> nt;
-    Batch<VT, true, true, true> cur;
-    nt.issue(P, t, ia, ad, x);
-    cur.load(nt.kb + 2 * tid, Entries<VT, true>(ja, al, au, nt.kb, nt.k1));
-    nt.window(x);
-    {
-        A *s_x, *s_y, *s_xw, *s_w;
-        uint16_t *s_rid;
-        int32_t *s_iv;
-        buffers(0, nt.T, s_x, s_y, s_xw, s_w, s_rid, s_iv);
-        nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_iv);
-    }
+    // the streaming tile; of the next tile only its entry range is kept (its
+    // record is read again when it becomes current)
+    PTile<E> cu;
+    int nkb = 0, nk1 = 0;
+    auto issue_next = [&](int tn, int cn) {
+        PTile<E> u;
+        u.read(P, tn);
+        stage_issue(u, cn);
+        nkb = u.kb;
+        nk1 = u.k1;
+    };
+    int t = ta, c = 0;
+    cu.read(P, t);
+    stage_issue(cu, 0);
+    Batch<VT, true, true, true> bA, bB;
+    bA.load(cu.kb + 2 * tid, Entries<VT, true>(ja, al, au, cu.kb, cu.k1));
+    wait_vm<BatchLoads<VT>::N>();
     __syncthreads();
+    stage_finish(cu, 0);
+    __syncthreads();
+    bool more = t + 1 < tb;
+    if (more) issue_next(t + 1, 1);
+    int qb = cu.kb;
 
-    for (int c = 0;; c ^= 1) {
-        settle_loads();
-        // the tile about to stream
-        const int r0 = nt.r0, T = nt.T, W = nt.W;
-        const int64_t goff = nt.goff;
-        const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
-        A *s_x, *s_y, *s_xw, *s_w;
-        uint16_t *s_rid;
-        int32_t *s_ivrow;
-        buffers(c, T, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
-        WindowMap wm;
-        wm.init(nt, s_ivrow);
-
-        const int tn = t + nslot;
-        const bool more = tn < hi;
-        Batch<VT, true, true, true> nb;
-        if (more) {
-            nt.issue(P, tn, ia, ad, x);
-            nb.load(nt.kb + 2 * tid, Entries<VT, true>(ja, al, au, nt.kb, nt.k1));
-        }
-        own_stream<VT, true, true>(
-            cur, E, s_rid, s_x, [](int) { return true; },
-            [&, wm](int j, A w) -> A {
-                const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
-                atomic_add(&s_y[idx], w);
-                return s_x[idx];
-            },
-            [&](int r, A v) { atomic_add(&s_y[r], v); },
-            [&]() {
-                if (more) nt.window(x);
-            });
-        __syncthreads();
-
-        for (int i = tid; i < T; i += 512) y[r0 + i] = (YT)s_y[i];
-        if (W) {
-            A *part = reinterpret_cast<A *>(P.partials) + goff;
-            for (int sl = tid; sl < W; sl += 512) part[sl] = s_w[sl];
-        }
-        if (!more) break;
+    // one batch step: cur holds the batch at qb; oth receives the next one.
+    // Returns true when the run is finished.
+    auto step = [&](Batch<VT, true, true, true> &cur, Batch<VT, true, true, true> &oth) -> bool {
+        const Entries<VT, true> Ec(ja, al, au, cu.kb, cu.k1);
         {
-            A *n_x, *n_y, *n_xw, *n_w;
-            uint16_t *n_rid;
-            int32_t *n_iv;
-            buffers(c ^ 1, nt.T, n_x, n_y, n_xw, n_w, n_rid, n_iv);
-            nt.stage(ia, ad, x, n_x, n_y, n_xw, n_w, n_rid, n_iv);
+            // one load site for the next batch (this tile's, the next tile's
+            // first, or an empty range that reads zeros without memory
+            // traffic), so the compiler counts the loads in flight exactly
+            const bool in_tile = qb + 4 * B < cu.k1;
+            const int lb = in_tile ? cu.kb : (more ? nkb : 0);
+            const int le = in_tile ? cu.k1 : (more ? nk1 : 0);
+            const int lq = in_tile ? qb + 4 * B : lb;
+            oth.load(lq + 2 * tid, Entries<VT, true>(ja, al, au, lb, le));
         }
+        const A *sx = bx(c);
+        A *sy = by(c);
+        const int r0 = cu.r0;
+        const PTile<E> &u = cu;
+        process_batch<VT, true, true>(
+            cur, qb + 2 * tid, Ec, brid(c), sx, [](int) { return true; },
+            [&](int j, A w) -> A {
+                const int idx = j >= r0 ? j - r0 : u.col_index(j);
+                atomic_add(&sy[idx], w);
+                return sx[idx];
+            },
+            [&](int r, A v) { atomic_add(&sy[r], v); });
+        qb += 4 * B;
+        if (qb < cu.k1) return false;
+        // tile done: every wave's copies for the next tile have landed (only
+        // the next tile's first batch may still be in flight)
+        wait_vm<BatchLoads<VT>::N>();
         __syncthreads();
-        cur = nb;
-        t = tn;
+        write_out(cu, c);
+        if (!more) return true;
+        ++t;
+        c ^= 1;
+        cu.read(P, t);
+        stage_finish(cu, c);
+        __syncthreads();
+        qb = cu.kb;
+        more = t + 1 < tb;
+        if (more) issue_next(t + 1, c ^ 1);
+        return false;
+    };
+    for (;;) {
+        if (step(bA, bB)) break;
+        if (step(bB, bA)) break;
     }
 }
 
@@ -1307,25 +1483,31 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         if (single) {
             const size_t lds = (size_t)lds_private(smax, emax, p->max_intervals, sizeof(Acc));
             if (p->o.persistent) {
-                if (B != 512 || p->max_intervals > 64 || 2 * align16((int64_t)lds) > kLdsBudget)
+                const int buf = (int)align16((int64_t)lds_private_padded(p->max_span_padded, emax, sizeof(Acc)));
+                if (B != kPersistentBlock || p->max_intervals > kRegIntervals || 2 * (int64_t)buf > kLdsBudget)
                     return CSRC_ERR_UNSUPPORTED;
-                const int buf = (int)align16((int64_t)lds);
-                auto kern = k_private_p<VT, YT, 2>;
+                auto kern = k_private_p<VT, YT>;
                 if (set_lds((const void *)kern, 2 * (size_t)buf)) return CSRC_ERR_HIP;
                 int grid = p->o.grid > 0 ? p->o.grid : p->persistent_grid.load(std::memory_order_relaxed);
                 if (grid <= 0) {
                     int per_cu = 0;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 512,
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kPersistentBlock,
                                                                      2 * (size_t)buf) != hipSuccess ||
                         per_cu < 1)
                         per_cu = 1;
                     grid = std::max(8, device_cus() * per_cu);
                     p->persistent_grid.store(grid, std::memory_order_relaxed);
                 }
-                kern<<<grid, 512, 2 * (size_t)buf, s>>>(P, p->ntiles, A->k, A->ia, A->ja, ad, al, au, x, y, smax,
-                                                       emax, buf);
+                kern<<<grid, kPersistentBlock, 2 * (size_t)buf, s>>>(P, p->ntiles, n, A->ia, A->ja, ad, al, au, x, y,
+                                                                     p->max_span_padded, emax, buf);
+            } else if (p->o.atomic_merge) {
+                k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
+                auto kern = k_private<VT, YT, true>;
+                if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+                kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
+                return hip_status(hipGetLastError());
             } else {
-                auto kern = k_private<VT, YT>;
+                auto kern = k_private<VT, YT, false>;
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
                 kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
             }

@@ -1,5 +1,6 @@
 """Reduced-precision storage (FP32 / BF16 values, FP32 x, FP32 accumulation),
-every variant, y in FP32 or FP64, with and without the compensated merge.
+every variant, y in FP32 or FP64, with and without the compensated merge
+(the atomic merge has no compensated form).
 
 Bars (Higham's bound for sums of m rounded products in any order):
 * against the FP64 oracle on the stored (dequantised) values and rounded x:
@@ -18,12 +19,15 @@ from tests.helpers import oracle_csrc, rel_inf
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "atomic", "private", "color", "owner"]
+VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_atomic"]
 
 
 def run(C, torch, host, x, variant, dtype, ydtype, transpose=False, **kw):
     A = C.Matrix(host, dtype)
-    plan = C.Plan(A, variant, ydtype=ydtype, **kw)
+    if variant == "private_atomic":
+        plan = C.Plan(A, "private", ydtype=ydtype, atomic_merge=1, **kw)
+    else:
+        plan = C.Plan(A, variant, ydtype=ydtype, **kw)
     xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32)
     y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
     (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
@@ -45,7 +49,7 @@ def test_reduced_precision_bounds(variant, dtype, ydtype):
     uv = R.UNIT_ROUNDOFF[dtype]
     m = R.row_terms(c)
     for transpose in (False, True):
-        for comp in (False, True):
+        for comp in ((False,) if variant == "private_atomic" else (False, True)):
             y = run(C, torch, host, x, variant, dtype, ydtype, transpose, compensated=comp)
             f = R.spmv_t if transpose else R.spmv
             ref_stored = f(c, xf, **ov)
