@@ -136,7 +136,12 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         p->vdtype = vdtype;
         p->o = o;
         if (p->o.block == 0)
-            p->o.block = (o.variant == CSRC_V_PLAIN || o.variant == CSRC_V_COLOR) ? 256 : 512;
+            // PRIVATE: 256 threads let six to eight tiles share a compute unit;
+            // the persistent schedule is written for 512
+            p->o.block = (o.variant == CSRC_V_PLAIN || o.variant == CSRC_V_COLOR ||
+                          (o.variant == CSRC_V_PRIVATE && !o.persistent))
+                             ? 256
+                             : 512;
         if (p->o.lanes == 0) p->o.lanes = auto_lanes(n, p->k);
         if (p->o.lanes == 1) p->o.lanes = 2;
         if (p->o.tile_work == 0)

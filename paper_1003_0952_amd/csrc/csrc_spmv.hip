@@ -75,15 +75,28 @@ __device__ __forceinline__ void rows_loop(int ib, int ie, int grp, int ngrp, int
 
 // ---------------------------------------------------------------- helpers
 
+// y[i * ldy + c] = 0 for rows i < n, columns c < r.  A contiguous block
+// (ldy == r) is cleared with 16-byte stores after a short unaligned head.
 template <class YT>
-__global__ void k_fill_zero(YT *__restrict__ y, int32_t n, int32_t r, int64_t ldy)
+__global__ __launch_bounds__(256) void k_fill_zero(YT *__restrict__ y, int32_t n, int32_t r, int64_t ldy)
 {
-    int64_t total = (int64_t)n * r;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t i = e / r, c = e - i * r;
-        y[i * ldy + c] = YT(0);
+    const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+    if (ldy == r) {
+        constexpr int V = 16 / sizeof(YT);
+        const int64_t count = (int64_t)n * r;
+        const int64_t mis = (int64_t)((reinterpret_cast<uintptr_t>(y) & 15) / sizeof(YT));
+        const int64_t head = mis ? min<int64_t>(count, V - mis) : 0;
+        if (gt < head) y[gt] = YT(0);
+        int4 *b = reinterpret_cast<int4 *>(y + head);
+        const int64_t nv = (count - head) / V;
+        for (int64_t v = gt; v < nv; v += gs) b[v] = make_int4(0, 0, 0, 0);
+        const int64_t t0 = head + nv * V;
+        if (t0 + gt < count) y[t0 + gt] = YT(0);
+        return;
     }
+    for (int64_t i = gt; i < n; i += gs)
+        for (int c = 0; c < r; ++c) y[i * ldy + c] = YT(0);
 }
 
 // last index i in [0, cnt) with key[i] <= v (key ascending, key[0] <= v)
@@ -634,14 +647,13 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     __syncthreads();
     settle_loads();
 
-    own_stream<VT, true, true>(
-        first, E, s_rid, s_x, [](int) { return true; },
-        [&, wm](int j, A w) -> A {
-            const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
-            atomic_add(&s_y[idx], w);
-            return s_x[idx];
-        },
-        [&](int r, A v) { atomic_add(&s_y[r], v); });
+    auto ent = [&, wm](int j, A w) -> A {
+        const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
+        atomic_add(&s_y[idx], w);
+        return s_x[idx];
+    };
+    auto flush = [&](int r, A v) { atomic_add(&s_y[r], v); };
+    own_stream<VT, true, true>(first, E, s_rid, s_x, [](int) { return true; }, ent, flush);
     __syncthreads();
 
     if (AM) {
@@ -1438,7 +1450,9 @@ static PlanDev plan_dev(const csrc_plan *p, void *ws)
 
 static int device_cus();
 
-static int fill_grid(int64_t count) { return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (count + 255) / 256)); }
+// workgroups of k_fill_zero for count values (about 16 per thread; fewer,
+// longer workgroups clear a large y fastest)
+static int fill_grid(int64_t count) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (count + 4095) / 4096)); }
 
 template <class VT, class YT, int G>
 static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *al_, const void *au_,

@@ -1,12 +1,13 @@
 """Build the learned selector: time every candidate on seeded matrices of the
 selector family, train the network on the GPU, evaluate on held-out matrices.
 
-  python -m paper_1003_0952_amd.train_selector campaign --count 2000 --db DB
+  python -m paper_1003_0952_amd.train_selector campaign --count 2240 --db DB
   python -m paper_1003_0952_amd.train_selector train --db DB
 
 The campaign is resumable (one JSON line per matrix; finished matrices are
 skipped) and stops after --budget seconds so it can run in several pieces.
-Matrices m >= --heldout-from are never trained on.
+Matrices m >= --big-from are drawn with the larger nnz cap.  Matrices in the
+--heldout ranges are never trained on.
 """
 
 import argparse
@@ -60,7 +61,9 @@ def campaign(args):
     def refill():
         # a bounded window of prepared matrices (each may be tens of MB)
         while queue and len(pending) < 2 * args.workers:
-            pending.append(pool.submit(_prepare, (queue.pop(0), args.nnz_cap)))
+            m = queue.pop(0)
+            cap = args.big_nnz_cap if m >= args.big_from else args.nnz_cap
+            pending.append(pool.submit(_prepare, (m, cap)))
 
     def results():
         refill()
@@ -109,7 +112,7 @@ def campaign(args):
             out.write(json.dumps(rec) + "\n")
             out.flush()
             count += 1
-            if count % 25 == 0:
+            if count % 25 == 0 or (m >= args.big_from and count % 5 == 0):
                 print(f"# {count} matrices, {time.time() - t0:.0f}s", flush=True)
             del plans, mats, xs, ys, A
             if time.time() - t0 > args.budget:
@@ -132,9 +135,13 @@ def load_db(path):
 
 
 def baseline_pick(times, default, fallback):
-    """The choice without a selector: the default candidate, or the fallback
-    where the default cannot run the matrix."""
-    return default if np.isfinite(times[default]) else fallback
+    """The choice without a selector: the default candidate, else the
+    fallback, else the plain kernel (which runs every matrix)."""
+    from .tuner import PLAIN
+    for c in (default, fallback, PLAIN):
+        if np.isfinite(times[c]):
+            return c
+    return PLAIN
 
 
 def evaluate(model, recs, default, fallback):
@@ -160,25 +167,38 @@ def evaluate(model, recs, default, fallback):
             "gain_vs_default_total_time": float(t_base / t_model)}
 
 
+def heldout_ranges(text):
+    """'1800:2000,2200:2240' -> [(1800, 2000), (2200, 2240)]"""
+    return [tuple(int(v) for v in part.split(":")) for part in text.split(",") if part]
+
+
+def is_heldout(m, ranges):
+    return any(a <= m < b for a, b in ranges)
+
+
 def train_cmd(args):
     import torch
     from paper_1003_0952_amd import selector as S, tuner as T
     recs = load_db(args.db)
-    train_r = [r for r in recs if r["m"] < args.heldout_from]
-    test_r = [r for r in recs if r["m"] >= args.heldout_from]
+    ho = heldout_ranges(args.heldout)
+    train_r = [r for r in recs if not is_heldout(r["m"], ho)]
+    test_r = [r for r in recs if is_heldout(r["m"], ho)]
     F = np.array([r["features"] for r in train_r], dtype=np.float32)
     y = np.array([r["best"] for r in train_r], dtype=np.int32)
     K = len(T.CANDIDATES)
     t0 = time.time()
     params, mean, scale, hist = S.train(torch, F, y, K, steps=args.steps, lr=args.lr, seed=args.seed)
     model = S.Selector(params, mean, scale)
-    rep = {"train_matrices": len(train_r), "heldout_matrices": len(test_r), "steps": args.steps,
+    big = [r for r in test_r if r["m"] >= args.big_from]
+    rep = {"train_matrices": len(train_r), "heldout_matrices": len(test_r), "heldout_ranges": args.heldout,
+           "steps": args.steps,
            "train_seconds": round(time.time() - t0, 2), "loss_first": hist[0], "loss_last": hist[-1],
            "label_histogram": np.bincount(y, minlength=K).tolist(),
            "candidates": [T.candidate_name(i) for i in range(K)], "default": T.candidate_name(T.DEFAULT),
            "fallback": T.candidate_name(T.FALLBACK),
            "train": evaluate(model, train_r, T.DEFAULT, T.FALLBACK),
-           "heldout": evaluate(model, test_r, T.DEFAULT, T.FALLBACK)}
+           "heldout": evaluate(model, test_r, T.DEFAULT, T.FALLBACK),
+           "heldout_large": evaluate(model, big, T.DEFAULT, T.FALLBACK) if big else None}
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
     model.save(args.model)
     with open(args.report, "w") as fh:
@@ -190,7 +210,9 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("campaign")
-    c.add_argument("--count", type=int, default=2000)
+    c.add_argument("--count", type=int, default=2240)
+    c.add_argument("--big-from", type=int, default=2000)
+    c.add_argument("--big-nnz-cap", type=float, default=3e7)
     c.add_argument("--db", default=os.path.join(DATA, "timings.jsonl"))
     c.add_argument("--nnz-cap", type=float, default=2e6)
     c.add_argument("--workers", type=int, default=10)
@@ -200,7 +222,8 @@ def main():
     t.add_argument("--db", default=os.path.join(DATA, "timings.jsonl"))
     t.add_argument("--model", default=os.path.join(DATA, "model.json"))
     t.add_argument("--report", default=os.path.join(DATA, "report.json"))
-    t.add_argument("--heldout-from", type=int, default=1800)
+    t.add_argument("--heldout", default="1800:2000,2200:2240")
+    t.add_argument("--big-from", type=int, default=2000)
     t.add_argument("--steps", type=int, default=3000)
     t.add_argument("--lr", type=float, default=3e-3)
     t.add_argument("--seed", type=int, default=0)

@@ -20,17 +20,19 @@ from . import api as C
 # (variant, plan options).  Order fixes the class index of the selector.
 CANDIDATES = [
     ("private", {"tile_work": 4096, "block": 256}),
-    ("private", {"tile_work": 8192, "block": 512}),
+    ("private", {"tile_work": 8192, "block": 256}),
     ("private", {"tile_work": 16384, "block": 512}),
+    ("private", {"tile_work": 4096, "block": 256, "atomic_merge": 1}),
+    ("private", {"tile_work": 8192, "block": 256, "atomic_merge": 1}),
+    ("private", {"tile_work": 16384, "block": 512, "atomic_merge": 1}),
     ("owner", {"tile_work": 8192, "block": 512}),
-    ("owner", {"tile_work": 16384, "block": 512}),
     ("atomic", {"tile_work": 8192, "block": 512}),
-    ("atomic", {"tile_work": 32768, "block": 512}),
     ("color", {}),
     ("plain", {}),
 ]
-DEFAULT = 1      # the fixed choice without a selector: private, 8192, 512 threads
-FALLBACK = 5     # ... or atomic, 8192, 512 threads where private cannot run
+DEFAULT = 1      # the fixed choice without a selector: private, 8192, 256 threads, merge pass
+FALLBACK = 7     # ... or atomic, 8192, 512 threads where private cannot run
+PLAIN = 9        # ... or the plain kernel, which runs every matrix
 
 
 def candidate_name(i):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1003_0952_amd import selector as S, tuner as T
-from paper_1003_0952_amd.train_selector import load_db, evaluate, baseline_pick
+from paper_1003_0952_amd.train_selector import load_db, evaluate, baseline_pick, heldout_ranges, is_heldout
 
 DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1003_0952_amd",
                     "selector_data")
@@ -23,10 +23,20 @@ def stored():
     return recs, model
 
 
+COUNT = 2240          # 2000 matrices up to 2e6 nnz, then 240 up to 3e7 nnz
+BIG_FROM = 2000
+HELDOUT = heldout_ranges("1800:2000,2200:2240")
+
+
+def heldout(recs):
+    return [r for r in recs if is_heldout(r["m"], HELDOUT)]
+
+
 def test_campaign_shape(stored):
     recs, _ = stored
-    assert len(recs) == 2000
-    assert {r["m"] for r in recs} == set(range(2000))
+    assert len(recs) == COUNT
+    assert {r["m"] for r in recs} == set(range(COUNT))
+    assert max(r["nnz"] for r in recs if r["m"] >= BIG_FROM) > 2e6
     fams = {r["spec"]["family"] for r in recs}
     assert fams == {"stencil", "banded", "fem3", "power"}
     for r in recs:
@@ -36,9 +46,9 @@ def test_campaign_shape(stored):
 
 def test_heldout_gain_over_fixed_choice(stored):
     recs, model = stored
-    held = [r for r in recs if r["m"] >= 1800]
+    held = heldout(recs)
     ev = evaluate(model, held, T.DEFAULT, T.FALLBACK)
-    assert ev["matrices"] == 200
+    assert ev["matrices"] == 240
     assert ev["gain_vs_default_geomean"] > 1.03      # faster than the fixed choice
     assert ev["regret_mean"] < 0.10                   # close to exhaustive tuning
     assert ev["exact_pick_rate"] > 0.6
@@ -51,19 +61,20 @@ def test_report_matches_stored_data(stored):
     recs, model = stored
     with open(os.path.join(DATA, "report.json")) as fh:
         rep = json.load(fh)
-    held = [r for r in recs if r["m"] >= 1800]
+    held = heldout(recs)
     ev = evaluate(model, held, T.DEFAULT, T.FALLBACK)
+    assert rep["heldout_matrices"] == len(held)
     assert rep["heldout"]["exact_pick_rate"] == pytest.approx(ev["exact_pick_rate"])
     assert rep["heldout"]["gain_vs_default_geomean"] == pytest.approx(ev["gain_vs_default_geomean"])
 
 
-@pytest.mark.parametrize("m", [1800, 1803, 1950])
+@pytest.mark.parametrize("m", [1800, 1803, 1950, 2201])
 def test_stored_features_are_the_library_features(stored, m):
     from synth import workloads as W
     import paper_1003_0952_amd as C
     recs, _ = stored
     rec = next(r for r in recs if r["m"] == m)
-    spec = W.family_spec(m, nnz_cap=2e6)
+    spec = W.family_spec(m, nnz_cap=3e7 if m >= BIG_FROM else 2e6)
     assert spec == rec["spec"]
     a, _ = W.family_member(spec)
     host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
