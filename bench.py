@@ -73,8 +73,9 @@ class Copies:
         self.yt = [torch.empty(n, dtype=ydt, device="cuda") for _ in self.mats]
 
 
-def time_plan(C, torch, cp, plan, steps, warmup, per_product=False):
-    """Mean ms per step (Ax + A^T x) over `steps` steps after `warmup`."""
+def time_plan(C, torch, cp, plan, steps, warmup):
+    """Mean ms per step (Ax then A^T x) over `steps` back-to-back steps after
+    `warmup`; HIP events only at the two ends of the timed region."""
     ydt = plan.ytorch
     if not cp.y or cp.y[0].dtype != ydt:
         cp.outputs(torch, ydt)
@@ -88,29 +89,33 @@ def time_plan(C, torch, cp, plan, steps, warmup, per_product=False):
     for s in range(warmup):
         step(s)
     torch.cuda.synchronize()
-    ev = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
     for s in range(steps):
-        if per_product:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            c = s % nc
-            e[0].record()
-            C.csrc_spmv(cp.mats[c], plan, cp.x[c], cp.y[c])
-            e[1].record()
-            C.csrc_spmv_t(cp.mats[c], plan, cp.x[c], cp.yt[c])
-            e[2].record()
-            ev.append(e)
-        else:
-            step(s)
+        step(s)
     t1.record()
     torch.cuda.synchronize()
-    total = t0.elapsed_time(t1)
-    prod = None
-    if per_product:
-        prod = [(e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])) for e in ev]
-    return total / steps, prod
+    return t0.elapsed_time(t1) / steps
+
+
+def time_products(C, torch, cp, plan, count, transpose):
+    """Mean ms per product over `count` back-to-back products of one kind
+    (y = A x, or y = A^T x), HIP events only at the two ends."""
+    nc = len(cp.mats)
+    f = C.csrc_spmv_t if transpose else C.csrc_spmv
+    out = cp.yt if transpose else cp.y
+    for s in range(3):
+        f(cp.mats[s % nc], plan, cp.x[s % nc], out[s % nc])
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for s in range(count):
+        f(cp.mats[s % nc], plan, cp.x[s % nc], out[s % nc])
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / count
 
 
 def kernel_source_hash():
@@ -130,10 +135,12 @@ def measured_traffic(workload, dtype, vname, vkw):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != kernel_source_hash() or d.get("variant") != vname or \
-            any(d.get("options", {}).get(k) != v for k, v in vkw.items()):
+    if d.get("source_hash") != kernel_source_hash():
         return None
-    return d["bytes_per_product"]
+    for e in d.get("entries", []):
+        if e["variant"] == vname and e["options"] == vkw:
+            return e["bytes_per_product"]
+    return None
 
 
 def cpu_baseline(host, x, budget_s=12.0):
@@ -161,11 +168,15 @@ def main():
     ap.add_argument("--dtype", default="f64")
     ap.add_argument("--variant", default="auto", help="auto, or a variant name")
     ap.add_argument("--tile-work", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--atomic-merge", type=int, default=0)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="copy 256 MiB on the device three times first (counter calibration)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copies", type=int, default=0)
-    ap.add_argument("--tune-steps", type=int, default=15)
+    ap.add_argument("--tune-steps", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the product is "
@@ -174,6 +185,14 @@ def main():
 
     import torch
     import paper_1003_0952_amd as C
+
+    if args.calibration_copy:
+        src = torch.ones(2**25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     t_setup = time.perf_counter()
     a, x = build_workload(args.workload)
@@ -204,7 +223,7 @@ def main():
             except C.CsrcError as e:
                 tuning.append({"candidate": T.candidate_name(i), "error": str(e)})
                 continue
-            ms, _ = time_plan(C, torch, cp, plan, args.tune_steps, 3)
+            ms = time_plan(C, torch, cp, plan, args.tune_steps, 3)
             tms[i] = ms
             tuning.append({"candidate": T.candidate_name(i), "ms_per_step": round(ms, 4)})
             print(f"# tune {T.candidate_name(i)} {ms:.4f} ms/step", file=sys.stderr, flush=True)
@@ -229,23 +248,29 @@ def main():
         vkw = {}
         if args.tile_work:
             vkw["tile_work"] = args.tile_work
+        if args.block:
+            vkw["block"] = args.block
+        if args.atomic_merge:
+            vkw["atomic_merge"] = args.atomic_merge
     if args.lanes:
         vkw["lanes"] = args.lanes
     plan = C.Plan(cp.mats[0], vname, **vkw)
     info = plan.info()
 
-    # --- timed region
-    ms, prods = time_plan(C, torch, cp, plan, args.steps, args.warmup, per_product=True)
-    fwd = float(np.mean([p[0] for p in prods]))
-    bwd = float(np.mean([p[1] for p in prods]))
-    per_prod_ms = (fwd + bwd) / 2
+    # --- timed region: back-to-back steps, events at its two ends; a product
+    # (all launches of one y = A x or y = A^T x) takes half a step
+    ms = time_plan(C, torch, cp, plan, args.steps, args.warmup)
+    per_prod_ms = ms / 2
+    # the two product kinds apart, in passes of their own
+    fwd = time_products(C, torch, cp, plan, min(args.steps, 50), False)
+    bwd = time_products(C, torch, cp, plan, min(args.steps, 50), True)
     gbs = 2 * B1 / (ms * 1e-3) / 1e9
     gfl = 2 * flops(n, k) / (ms * 1e-3) / 1e9
 
     plain = None
     if not args.no_plain:
         pplan = C.Plan(cp.mats[0], "plain")
-        pms, _ = time_plan(C, torch, cp, pplan, max(10, args.steps // 4), 3)
+        pms = time_plan(C, torch, cp, pplan, max(10, args.steps // 4), 3)
         plain = {"ms_per_step": round(pms, 4), "value": round(2 * B1 / (pms * 1e-3) / 1e9, 1),
                  "gflops": round(2 * flops(n, k) / (pms * 1e-3) / 1e9, 1),
                  "pct_hbm_peak": round(100 * 2 * B1 / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)}
@@ -271,6 +296,11 @@ def main():
                "gflops": round(2 * flops(n, k) / dt / 1e9, 3)}
 
     ach = B1 / (per_prod_ms * 1e-3) / 1e9
+    if vname == "private":
+        launches = ("one product = k_fill_zero + k_private (atomic merge)" if vkw.get("atomic_merge")
+                    else "one product = k_private + k_merge")
+    else:
+        launches = f"one product = all launches of the {vname} variant"
     traffic = measured_traffic(args.workload, args.dtype, vname, vkw)
     out = {
         "metric": METRIC,
@@ -299,7 +329,8 @@ def main():
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"{vname} product (all its launches)", "bytes_per_launch": B1},
+                     "kernel": launches, "bytes_per_launch": B1,
+                     "duration_us": round(per_prod_ms * 1e3, 2)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
