@@ -13,6 +13,11 @@ candidate timed on this matrix); the learned selector's pick for the same
 matrix, and its regret against the tuned choice, are reported beside it.  The
 plain FP64 kernel (one thread per row, global atomics) is timed the same way
 as the baseline.  Prints one JSON line.
+
+Other workloads: hex100_random / hex100_rcm (the same mesh renumbered),
+tet80 (3-dof tetrahedral mesh, for the reduced-precision forms) and batch256
+(256 matrices of uneven size with 1..32 right-hand sides each, run as one
+persistent launch under a HIP graph).
 """
 
 import argparse
@@ -159,6 +164,155 @@ def cpu_baseline(host, x, budget_s=12.0):
     return reps, dt
 
 
+BATCH_COUNT = 256
+
+
+def bench_batch(args):
+    """Batched products: 256 seeded matrices (n log-uniform 1e3..2e5, 2-D
+    9-point and 3-D 27-point patterns), each with 1..32 right-hand sides, in
+    one persistent launch replayed as a HIP graph.  A step is Y = A X then
+    Y = A^T X for every matrix of the batch (two graph launches)."""
+    import torch
+    import paper_1003_0952_amd as C
+    from synth import workloads as W
+    from paper_1003_0952_amd import tuner as T
+    from oracle import reference as R
+
+    t_setup = time.perf_counter()
+    vb = {"f64": 8, "f32": 4, "bf16": 2}[args.dtype]
+    xb = 8 if args.dtype == "f64" else 4
+    ydt = "f64" if args.dtype == "f64" else "f32"
+    members, mats, Xs = [], [], []
+    B1 = F1 = 0
+    nsum = ksum = 0
+    for m in range(BATCH_COUNT):
+        a, X = W.batch_member(m)
+        host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+        A = C.Matrix(host, args.dtype)
+        mats.append(A)
+        Xs.append(torch.from_numpy(X).to("cuda", A.xdtype))
+        members.append((host, X))
+        r = X.shape[1]
+        B1 += algorithmic_bytes(host["n"], host["k"], vb, xb, xb, r)
+        F1 += flops(host["n"], host["k"], r)
+        nsum += host["n"]
+        ksum += host["k"]
+    rs = [X.shape[1] for X in Xs]
+    print(f"# setup {time.perf_counter() - t_setup:.1f}s matrices={BATCH_COUNT} rows={nsum} k={ksum} "
+          f"bytes/product={B1}", file=sys.stderr, flush=True)
+
+    def make(kw):
+        bp = C.BatchPlan(mats, rs, ydtype=ydt, **kw)
+        Ys = [torch.empty((A.n, r), dtype=bp.ytorch, device="cuda") for A, r in zip(mats, rs)]
+        bp.bind(Xs, Ys)
+        return bp, Ys, bp.graph(False), bp.graph(True)
+
+    def time_graphs(g, gt, steps, warmup):
+        for _ in range(warmup):
+            C.BatchPlan.launch_graph(g)
+            C.BatchPlan.launch_graph(gt)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            C.BatchPlan.launch_graph(g)
+            C.BatchPlan.launch_graph(gt)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
+    # --- partition / tile shape: every batch candidate timed, fastest kept
+    tuning = []
+    best = None
+    cands = T.BATCH_CANDIDATES
+    if args.tile_work or args.block:
+        cands = [{"tile_work": args.tile_work, "block": args.block}]
+    for kw in cands:
+        try:
+            bp, Ys, g, gt = make(kw)
+        except C.CsrcError as e:
+            tuning.append({"candidate": kw, "error": str(e)})
+            continue
+        ms = time_graphs(g, gt, args.tune_steps, 2)
+        tuning.append({"candidate": kw, "ms_per_step": round(ms, 4)})
+        print(f"# tune {kw} {ms:.4f} ms/step", file=sys.stderr, flush=True)
+        if best is None or ms < best[1]:
+            best = (kw, ms)
+        del bp, Ys, g, gt
+    kw = best[0]
+    bp, Ys, g, gt = make(kw)
+    ms = time_graphs(g, gt, args.steps, args.warmup)
+
+    # parity spot check: the forward and transpose graphs on sampled members
+    sample = sorted({0, 1, 64, 127, 128, 200, 254, 255, max(range(BATCH_COUNT), key=lambda i: mats[i].n)})
+    err = {"Ax": 0.0, "ATx": 0.0}
+    for tr, gg in ((False, g), (True, gt)):
+        C.BatchPlan.launch_graph(gg)
+        torch.cuda.synchronize()
+        for i in sample:
+            host, X = members[i]
+            c = {kk: host[kk] for kk in ("n", "k", "ia", "ja", "ad", "al", "au")}
+            f = R.spmv_t if tr else R.spmv
+            ref = np.stack([f(c, np.ascontiguousarray(X[:, j])) for j in range(X.shape[1])], axis=1)
+            got = Ys[i].double().cpu().numpy()
+            e = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            err["ATx" if tr else "Ax"] = max(err["ATx" if tr else "Ax"], e)
+
+    cpu = None
+    if not args.no_cpu:
+        # oracle on the leading members until the time budget is spent
+        t0 = time.perf_counter()
+        done_b = 0
+        done_m = 0
+        for i in range(BATCH_COUNT):
+            host, X = members[i]
+            c = {kk: host[kk] for kk in ("n", "k", "ia", "ja", "ad", "al", "au")}
+            for j in range(X.shape[1]):
+                xj = np.ascontiguousarray(X[:, j])
+                R.spmv(c, xj)
+                R.spmv_t(c, xj)
+            done_b += 2 * algorithmic_bytes(host["n"], host["k"], vb, xb, xb, X.shape[1])
+            done_m += 1
+            if time.perf_counter() - t0 > 12.0:
+                break
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(done_b / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"members 0..{done_m - 1} of the batch, every right-hand side, y=Ax and y=A^T x, "
+                         f"plain sequential C oracle (FP64 values), {dt:.1f} s"}
+
+    gbs = 2 * B1 / (ms * 1e-3) / 1e9
+    ach = gbs
+    out = {
+        "metric": METRIC,
+        "value": round(gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"batch{BATCH_COUNT}_{args.dtype}", "matrices": BATCH_COUNT, "rows": nsum,
+                   "k": ksum, "rhs_total": int(sum(rs)), **kw,
+                   "step": "graph of Y=AX for all matrices, then graph of Y=A^T X"},
+        "gflops": round(2 * F1 / (ms * 1e-3) / 1e9, 1),
+        "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "max_rel_err_vs_oracle": err,
+        "parity_sample": sample,
+        "tuning": tuning,
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "one product = k_batch_tiles + k_batch_merge (one graph launch)",
+                     "bytes_per_launch": B1, "duration_us": round(ms / 2 * 1e3, 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +336,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; the product is "
                           "measured at one GPU's shard shape (see the design notes for sharding)"}))
         sys.exit(2)
+
+    if args.workload.startswith("batch"):
+        bench_batch(args)
+        return
 
     import torch
     import paper_1003_0952_amd as C

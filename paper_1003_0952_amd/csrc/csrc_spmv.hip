@@ -364,7 +364,7 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, co
 template <class VT>
 __device__ __forceinline__ void stage_rows(int r0, int T, const typename VT::V *__restrict__ ad,
                                            const typename VT::X *__restrict__ x, typename VT::A *s_x,
-                                           typename VT::A *s_y, int64_t ldx = 1)
+                                           typename VT::S *s_y, int64_t ldx = 1)
 {
     using A = typename VT::A;
     for (int i = threadIdx.x; i < T; i += blockDim.x) {
@@ -392,10 +392,11 @@ __global__ __launch_bounds__(512) void k_atomic(const int32_t *__restrict__ tile
                                                 YT *__restrict__ y, int64_t ldy, int tmax)
 {
     using A = typename VT::A;
+    using S = typename VT::S;
     extern __shared__ __align__(16) unsigned char lds[];
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_y = s_x + tmax;
-    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16(2 * (int64_t)tmax * sizeof(A)));
+    S *s_y = reinterpret_cast<S *>(lds + align16((int64_t)tmax * sizeof(A)));
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + lds_xs(tmax, sizeof(A)));
     const int tid = threadIdx.x, B = blockDim.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = tiles[t], r1 = tiles[t + 1], T = r1 - r0;
@@ -524,8 +525,9 @@ struct NextTile {
     // Write the tile into LDS (layout of k_private).  Rows and slots past
     // the first S blockDim.x are loaded here.  Every thread calls it.
     __device__ __forceinline__ void stage(const int32_t *__restrict__ ia, const typename VT::V *__restrict__ ad,
-                                          const typename VT::X *__restrict__ x, A *s_x, A *s_y, A *s_xw, A *s_w,
-                                          uint16_t *s_rid, int32_t *s_ivrow) const
+                                          const typename VT::X *__restrict__ x, A *s_x, typename VT::S *s_y,
+                                          A *s_xw, typename VT::S *s_w, uint16_t *s_rid,
+                                          int32_t *s_ivrow) const
     {
         const int tid = threadIdx.x, B = blockDim.x;
 #pragma unroll
@@ -556,7 +558,7 @@ struct NextTile {
             const int sl = tid + s * B;
             if (sl < W) {
                 s_xw[sl] = xw[s];
-                s_w[sl] = A(0);
+                s_w[sl] = 0;
             }
         }
         for (int base = S * B; base < W; base += B) {
@@ -564,7 +566,7 @@ struct NextTile {
             const int row = window_row(sl);
             if (sl < W) {
                 s_xw[sl] = (A)x[row];
-                s_w[sl] = A(0);
+                s_w[sl] = 0;
             }
         }
     }
@@ -621,12 +623,13 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
                                                  YT *__restrict__ y, int smax, int emax)
 {
     using A = typename VT::A;
+    using S = typename VT::S;
     extern __shared__ __align__(16) unsigned char lds[];
     // x of the T own rows then the window slots; sums likewise: an entry's
     // target is one index into both
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_y = s_x + smax;
-    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16(2 * (int64_t)smax * sizeof(A)));
+    S *s_y = reinterpret_cast<S *>(lds + align16((int64_t)smax * sizeof(A)));
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + lds_xs(smax, sizeof(A)));
     int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                                    align16(((int64_t)emax + 4) * 2));
 
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     NextTile<VT, 2> nt;
     nt.issue(P, t, ia, ad, x);
     A *s_xw = s_x + nt.T;
-    A *s_w = s_y + nt.T;
+    S *s_w = s_y + nt.T;
     const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
     Batch<VT, true, true, true> first;
     first.load(nt.kb + 2 * tid, E);
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     for (int i = tid; i < T; i += B) y[r0 + i] = (YT)s_y[i];
     if (W) {
         A *part = reinterpret_cast<A *>(P.partials) + nt.goff;
-        for (int sl = tid; sl < W; sl += B) part[sl] = s_w[sl];
+        for (int sl = tid; sl < W; sl += B) part[sl] = (A)s_w[sl];
     }
 }
 
@@ -788,10 +791,13 @@ __global__ __launch_bounds__(kPersistentBlock) void k_private_p(PlanDev P, int n
     const int tb = lo + (int)((int64_t)(hi - lo) * (slot + 1) / nslot);
     if (ta >= tb) return;
 
+    using S = typename VT::S;
     auto bx = [&](int c) { return reinterpret_cast<A *>(lds + (size_t)c * buf_bytes); };
-    auto by = [&](int c) { return bx(c) + smax; };
+    auto by = [&](int c) {
+        return reinterpret_cast<S *>(lds + (size_t)c * buf_bytes + align16((int64_t)smax * sizeof(A)));
+    };
     auto brid = [&](int c) {
-        return reinterpret_cast<uint16_t *>(lds + (size_t)c * buf_bytes + align16(2 * (int64_t)smax * sizeof(A)));
+        return reinterpret_cast<uint16_t *>(lds + (size_t)c * buf_bytes + lds_xs(smax, sizeof(A)));
     };
     const __amdgpu_buffer_rsrc_t rx = make_rsrc(x, (uint32_t)n * (uint32_t)sizeof(A));
 
@@ -825,7 +831,7 @@ __global__ __launch_bounds__(kPersistentBlock) void k_private_p(PlanDev P, int n
     // tile u's sums and row ids in buffer c (its x values have landed)
     auto stage_finish = [&](const PTile<E> &u, int c) {
         const A *sx = bx(c);
-        A *sy = by(c);
+        S *sy = by(c);
         uint16_t *rid = brid(c);
         if (tid < u.T) {
             sy[tid] = nad * sx[tid];
@@ -836,17 +842,17 @@ __global__ __launch_bounds__(kPersistentBlock) void k_private_p(PlanDev P, int n
             const int q1 = ia[u.r0 + i + 1];
             for (int q = ia[u.r0 + i]; q < q1; ++q) rid[q - u.kb] = (uint16_t)i;
         }
-        for (int i = u.T + tid; i < u.span; i += B) sy[i] = A(0);
+        for (int i = u.T + tid; i < u.span; i += B) sy[i] = 0;
         const int len = ((u.k1 - u.kb) + 3) & ~1;
         for (int q = tid; q < u.k0 - u.kb; q += B) rid[q] = kNoRow;
         for (int q = (u.k1 - u.kb) + tid; q < len; q += B) rid[q] = kNoRow;
     };
     auto write_out = [&](const PTile<E> &u, int c) {
-        const A *sy = by(c);
+        const S *sy = by(c);
         for (int i = tid; i < u.T; i += B) y[u.r0 + i] = (YT)sy[i];
         if (u.W) {
             A *part = reinterpret_cast<A *>(P.partials) + u.goff;
-            for (int sl = tid; sl < u.W; sl += B) part[sl] = sy[u.slot_index(sl)];
+            for (int sl = tid; sl < u.W; sl += B) part[sl] = (A)sy[u.slot_index(sl)];
         }
     };
 
@@ -889,7 +895,7 @@ __global__ __launch_bounds__(kPersistentBlock) void k_private_p(PlanDev P, int n
             oth.load(lq + 2 * tid, Entries<VT, true>(ja, al, au, lb, le));
         }
         const A *sx = bx(c);
-        A *sy = by(c);
+        S *sy = by(c);
         const int r0 = cu.r0;
         const PTile<E> &u = cu;
         process_batch<VT, true, true>(
@@ -984,11 +990,13 @@ __global__ __launch_bounds__(512) void k_owner(PlanDev P, int64_t kend, const in
                                                YT *__restrict__ y, int tmax, int pmax, int emax)
 {
     using A = typename VT::A;
+    using S = typename VT::S;
     extern __shared__ __align__(16) unsigned char lds[];
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_y = s_x + tmax;
-    A *s_xp = s_y + tmax;
-    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + pmax) * sizeof(A)));
+    A *s_xp = s_x + tmax;
+    const int64_t xbytes = align16(((int64_t)tmax + pmax) * sizeof(A));
+    S *s_y = reinterpret_cast<S *>(lds + xbytes);
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + xbytes + align16((int64_t)tmax * sizeof(S)));
 
     const int tid = threadIdx.x, B = blockDim.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -1064,8 +1072,8 @@ template <> struct MmCols<B16T> { static constexpr int C = 8; };
 // Process the C columns of one stored entry q of row r (relative) with column
 // j: gather into acc[], scatter au * x_r into the LDS slot scat[], gather x_j
 // from xj[] (both C-wide rows of LDS or, for xj, of global memory).
-template <int C, class A>
-__device__ __forceinline__ void mm_entry(A a, A u, const A *xr, const A *xj, A *scat, A (&acc)[C])
+template <int C, class A, class S>
+__device__ __forceinline__ void mm_entry(A a, A u, const A *xr, const A *xj, S *scat, A (&acc)[C])
 {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -1087,13 +1095,14 @@ __device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, int64_t
                                                 int emax, unsigned char *lds)
 {
     using A = typename VT::A;
+    using S = typename VT::S;
     constexpr int C = MmCols<VT>::C;
+    const int64_t nv = ((int64_t)tmax + wmax) * C;
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_y = s_x + (int64_t)tmax * C;
-    A *s_xw = s_y + (int64_t)tmax * C;
-    A *s_w = s_xw + (int64_t)wmax * C;
-    uint16_t *s_rid =
-        reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + 2 * wmax) * C * sizeof(A)));
+    A *s_xw = s_x + (int64_t)tmax * C;
+    S *s_y = reinterpret_cast<S *>(lds + align16(nv * sizeof(A)));
+    S *s_w = s_y + (int64_t)tmax * C;
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + lds_xs(nv, sizeof(A)));
     int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
                                                    align16(((int64_t)emax + 4) * 2));
     const int tid = threadIdx.x, B = blockDim.x;
@@ -1122,7 +1131,7 @@ __device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, int64_t
             const int sl = e / C, c = e % C;
             const int k = upper_index(s_ivslot, NI, sl);
             s_xw[e] = c < nc ? (A)X[(int64_t)(s_ivrow[k] + (sl - s_ivslot[k])) * ldx + cc + c] : A(0);
-            s_w[e] = A(0);
+            s_w[e] = 0;
         }
         __syncthreads();
         settle_loads();
@@ -1169,7 +1178,7 @@ __device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, int64_t
             A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0] * r;
             for (int e = tid; e < W * C; e += B) {
                 const int sl = e / C, c = e % C;
-                if (c < nc) part[(int64_t)sl * r + cc + c] = s_w[e];
+                if (c < nc) part[(int64_t)sl * r + cc + c] = (A)s_w[e];
             }
         }
     }
@@ -1276,12 +1285,14 @@ __global__ __launch_bounds__(512) void k_owner_mm(PlanDev P, int64_t kend, const
                                                   int emax)
 {
     using A = typename VT::A;
+    using S = typename VT::S;
     constexpr int C = MmCols<VT>::C;
     extern __shared__ __align__(16) unsigned char lds[];
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_y = s_x + (int64_t)tmax * C;
-    A *s_xp = s_y + (int64_t)tmax * C;
-    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + align16((2 * (int64_t)tmax + pmax) * C * sizeof(A)));
+    A *s_xp = s_x + (int64_t)tmax * C;
+    const int64_t xbytes = align16(((int64_t)tmax + pmax) * C * sizeof(A));
+    S *s_y = reinterpret_cast<S *>(lds + xbytes);
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + xbytes + align16((int64_t)tmax * C * sizeof(S)));
     const int tid = threadIdx.x, B = blockDim.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;

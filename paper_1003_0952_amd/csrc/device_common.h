@@ -7,13 +7,17 @@
 namespace csrc {
 
 // ---- value types --------------------------------------------------------
-// Storage V, source-vector X and accumulator A types per storage dtype:
-//   F64 storage: double / double / double
-//   F32 storage: float  / float  / float
-//   BF16 storage: uint16 (bfloat16 bits) / float / float
-struct F64T { using V = double;   using X = double; using A = double; };
-struct F32T { using V = float;    using X = float;  using A = float;  };
-struct B16T { using V = uint16_t; using X = float;  using A = float;  };
+// Storage V, source-vector X and accumulator A types per storage dtype, and
+// S, the type of the LDS sums that take scattered adds:
+//   F64 storage: double / double / double, sums double
+//   F32 storage: float  / float  / float,  sums double
+//   BF16 storage: uint16 (bfloat16 bits) / float / float, sums double
+// Products, row sums, partials and the merge use A; only the LDS sums are
+// FP64 for every storage type, because the LDS of gfx950 executes ds_add_f64
+// at about twenty times the rate of ds_add_f32.
+struct F64T { using V = double;   using X = double; using A = double; using S = double; };
+struct F32T { using V = float;    using X = float;  using A = float;  using S = double; };
+struct B16T { using V = uint16_t; using X = float;  using A = float;  using S = double; };
 
 __device__ __forceinline__ double ldv(const double *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const float *p, int64_t i) { return p[i]; }

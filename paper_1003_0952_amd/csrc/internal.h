@@ -26,39 +26,43 @@ constexpr int kMaxTileRows = 2048;   // rows per tile (per-row state lives in LD
 constexpr int kPullRows = 1024;       // rows per pull chunk (OWNER)
 constexpr int kPullEntries = 16384;   // stored entries per pull chunk (OWNER)
 
-// Dynamic LDS of the flat tile kernels (acc = accumulator bytes).  Row ids
-// of a block's entries are uint16, padded by 4.
+// Dynamic LDS of the flat tile kernels (acc = accumulator bytes).  The LDS
+// sums that take scattered adds are FP64 for every storage type
+// (kSumBytes).  x values come first, then the sums, each region 16-byte
+// aligned (lds_xs); row ids of a block's entries are uint16, padded by 4.
 //   PRIVATE: x of own rows then window slots, sums of own rows then window
 //            slots (each sized by the largest rows + slots of one tile, smax);
 //            row ids; window interval starts and slots
-//   OWNER:   x, y of own rows; x of pulled rows; row ids
-//   ATOMIC:  x, y of own rows; row ids
+//   OWNER:   x of own rows and of pulled rows; sums of own rows; row ids
+//   ATOMIC:  x, sums of own rows; row ids
+constexpr int kSumBytes = 8;
+constexpr int64_t lds_xs(int64_t n, int acc) { return align16(n * acc) + align16(n * kSumBytes); }
 inline int64_t lds_private(int64_t smax, int64_t emax, int64_t ivmax, int acc)
 {
-    return align16(2 * smax * acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+    return lds_xs(smax, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
 // one buffer of the persistent PRIVATE kernel: x and sums of own rows and
-// window intervals, each padded to 16-byte chunks (spad values), row ids
+// window intervals, each padded to 16-byte chunks of x (spad values), row ids
 inline int64_t lds_private_padded(int64_t spad, int64_t emax, int acc)
 {
-    return align16(2 * spad * acc) + align16((emax + 4) * 2);
+    return lds_xs(spad, acc) + align16((emax + 4) * 2);
 }
 inline int64_t lds_owner(int64_t tmax, int64_t pmax, int64_t emax, int acc)
 {
-    return align16((2 * tmax + pmax) * acc) + align16((emax + 4) * 2);
+    return align16((tmax + pmax) * acc) + align16(tmax * kSumBytes) + align16((emax + 4) * 2);
 }
 inline int64_t lds_atomic(int64_t tmax, int64_t emax, int acc)
 {
-    return align16(2 * tmax * acc) + align16((emax + 4) * 2);
+    return lds_xs(tmax, acc) + align16((emax + 4) * 2);
 }
 // multi-column forms: C columns of each per-row and per-slot array
 inline int64_t lds_private_mm(int64_t tmax, int64_t wmax, int64_t emax, int64_t ivmax, int acc, int C)
 {
-    return align16((2 * tmax + 2 * wmax) * C * acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+    return lds_xs((tmax + wmax) * C, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
 inline int64_t lds_owner_mm(int64_t tmax, int64_t pmax, int64_t emax, int acc, int C)
 {
-    return align16((2 * tmax + pmax) * C * acc) + align16((emax + 4) * 2);
+    return align16((tmax + pmax) * C * acc) + align16(tmax * C * kSumBytes) + align16((emax + 4) * 2);
 }
 inline int mm_columns(int32_t vdtype) { return vdtype == CSRC_F64 ? 4 : 8; }
 
