@@ -43,8 +43,7 @@ extern "C" int csrc_batch_plan_create(int32_t nmat, const int32_t *n, const int3
             b->plans.push_back(p);
             b->n.push_back(n[m]);
             b->r.push_back(r[m]);
-            b->tmax = std::max(b->tmax, p->max_tile_rows);
-            b->wmax = std::max(b->wmax, p->max_window);
+            b->smax = std::max(b->smax, p->max_span);
             b->emax = std::max(b->emax, p->max_tile_entries);
             b->ivmax = std::max(b->ivmax, p->max_intervals);
             b->part_off.push_back(part_bytes);
@@ -61,7 +60,7 @@ extern "C" int csrc_batch_plan_create(int32_t nmat, const int32_t *n, const int3
                     b->mitems.push_back(mb);
                 }
         }
-        b->lds = csrc::lds_private_mm(b->tmax, b->wmax, b->emax, b->ivmax, acc, C);
+        b->lds = csrc::lds_private_mm(b->smax, b->emax, b->ivmax, acc, C);
         if (b->lds > csrc::kLdsBudget) { delete b; return CSRC_ERR_UNSUPPORTED; }
         // longest items first, so the grid stride ends with short items
         std::stable_sort(work.begin(), work.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });

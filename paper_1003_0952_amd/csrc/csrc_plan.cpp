@@ -270,8 +270,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             }
             if (p->o.max_rhs > 1)
                 p->lds_bytes = std::max(p->lds_bytes,
-                                        csrc::lds_private_mm(p->max_tile_rows, p->max_window, p->max_tile_entries,
-                                                             p->max_intervals, acc, csrc::mm_columns(vdtype)));
+                                        csrc::lds_private_mm(p->max_span, p->max_tile_entries, p->max_intervals,
+                                                             acc, csrc::mm_columns(vdtype)));
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 

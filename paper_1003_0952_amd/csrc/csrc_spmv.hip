@@ -1069,164 +1069,284 @@ template <class VT> struct MmCols { static constexpr int C = 4; };
 template <> struct MmCols<F32T> { static constexpr int C = 8; };
 template <> struct MmCols<B16T> { static constexpr int C = 8; };
 
-// Process the C columns of one stored entry q of row r (relative) with column
-// j: gather into acc[], scatter au * x_r into the LDS slot scat[], gather x_j
-// from xj[] (both C-wide rows of LDS or, for xj, of global memory).
-template <int C, class A, class S>
-__device__ __forceinline__ void mm_entry(A a, A u, const A *xr, const A *xj, S *scat, A (&acc)[C])
-{
+// Window of a PRIVATE tile read from its record: slot of a column below the
+// tile and row of a slot.  With at most kRecIntervals intervals both come
+// from compares over the record's interval table (held in registers);
+// otherwise from binary searches over the LDS copy of the interval list.
+struct RecWindow {
+    int n;
+    i8v row, slot;                      // unused entries: INT32_MAX
+    const int32_t *s_row, *s_slot;
+
+    __device__ __forceinline__ void init(const TileRec *R, const int32_t *s_iv)
+    {
+        n = R->ni;
+        row = *reinterpret_cast<const i8v *>(R->ivrow);
+        slot = *reinterpret_cast<const i8v *>(R->ivslot);
+        s_row = s_iv;
+        s_slot = s_iv + n;
+    }
+    __device__ __forceinline__ int slot_of(int j) const
+    {
+        if (n <= kRecIntervals) {
+            int o = slot[0] - row[0];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        atomic_add(&scat[c], u * xr[c]);
-        acc[c] += a * xj[c];
+            for (int k = 1; k < kRecIntervals; ++k) o = j >= row[k] ? slot[k] - row[k] : o;
+            return j + o;
+        }
+        const int k = upper_index(s_row, n, j);
+        return s_slot[k] + (j - s_row[k]);
+    }
+    __device__ __forceinline__ int row_of(int sl) const
+    {
+        if (n <= kRecIntervals) {
+            int o = row[0] - slot[0];
+#pragma unroll
+            for (int k = 1; k < kRecIntervals; ++k) o = sl >= slot[k] ? row[k] - slot[k] : o;
+            return sl + o;
+        }
+        const int k = upper_index(s_slot, n, sl);
+        return s_row[k] + (sl - s_slot[k]);
+    }
+};
+
+// One batch of the multi-column stream (lane pairs at qb and qb + 2B): each
+// entry of row i (relative) with column j scatters au x_i into the sums at
+// index idx = j - r0 (own row) or T + slot(j) (window slot), C columns at
+// once, and gathers al x_j; a lane's pair of one row is added to the row's
+// sums once.  LDS arrays are column-major with leading dimension ld, so the
+// lanes of one instruction touch one column (8-byte stride between indices,
+// as in the single-vector kernels) instead of C-wide rows that alias onto a
+// few banks.  Columns from nc on are padding and skipped (nc is uniform).
+template <class VT, int C, class Batch_>
+__device__ __forceinline__ void process_batch_mm(const Batch_ &cur, int qb, int kb, int k1,
+                                                 const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
+                                                 typename VT::S *s_y, int ld, int r0, int T, const RecWindow &wm,
+                                                 int nc)
+{
+    using A = typename VT::A;
+    using S = typename VT::S;
+    const int half = 2 * (int)blockDim.x;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+        const int q = qb + half * sp;
+        const uint32_t rv = q < k1 ? *reinterpret_cast<const uint32_t *>(s_rid + (q - kb)) : 0xFFFFFFFFu;
+        const int ra = (int)(rv & 0xFFFF), rb = (int)(rv >> 16);
+        A g[2][C];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = h ? rb : ra;
+#pragma unroll
+            for (int c = 0; c < C; ++c) g[h][c] = A(0);
+            if (row == (int)kNoRow) continue;
+            const int j = cur.j[sp][h];
+            const int idx = j >= r0 ? j - r0 : T + wm.slot_of(j);
+            A xi[C], xj[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                xi[c] = s_x[c * ld + row];
+                xj[c] = s_x[c * ld + idx];
+            }
+            const A a = cur.a[sp][h], u = cur.u[sp][h];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (c < nc) atomic_add(&s_y[c * ld + idx], (S)(u * xi[c]));
+                g[h][c] = a * xj[c];
+            }
+        }
+        if (ra == rb) {
+            if (ra != (int)kNoRow) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (c < nc) atomic_add(&s_y[c * ld + ra], (S)(g[0][c] + g[1][c]));
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = h ? rb : ra;
+                if (row == (int)kNoRow) continue;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (c < nc) atomic_add(&s_y[c * ld + row], (S)g[h][c]);
+            }
+        }
     }
 }
 
-// One PRIVATE tile t of a product with r columns (r >= 1).  Used by the
+// One PRIVATE tile t of a product with r columns (r >= 1), C columns at a
+// time; chunks after the first re-read the tile's entries from L2 (temporal
+// loads).  LDS: x of the T own rows then the W window slots, one column after
+// the other (leading dimension mm_ld(smax)); the FP64 sums likewise; row ids;
+// the interval list when the tile has more intervals than its record holds.  Own rows go to Y, window sums to the
+// partial buffer (r values per slot) for the merge pass.  Used by the
 // multi-column kernel and by the batched persistent kernel.
 template <class VT, class YT>
-__device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, int64_t kend,
-                                                const int32_t *__restrict__ ia, const int32_t *__restrict__ ja,
+__device__ __forceinline__ void private_tile_mm(const PlanDev &P, int t, const int32_t *__restrict__ ia,
+                                                const int32_t *__restrict__ ja,
                                                 const typename VT::V *__restrict__ ad,
                                                 const typename VT::V *__restrict__ al,
                                                 const typename VT::V *__restrict__ au,
                                                 const typename VT::X *__restrict__ X, int64_t ldx,
-                                                YT *__restrict__ Y, int64_t ldy, int r, int tmax, int wmax,
-                                                int emax, unsigned char *lds)
+                                                YT *__restrict__ Y, int64_t ldy, int r, int smax, int emax,
+                                                unsigned char *lds)
 {
     using A = typename VT::A;
     using S = typename VT::S;
     constexpr int C = MmCols<VT>::C;
-    const int64_t nv = ((int64_t)tmax + wmax) * C;
+    const int ld = mm_ld(smax);
+    const int64_t nv = (int64_t)ld * C;
     A *s_x = reinterpret_cast<A *>(lds);
-    A *s_xw = s_x + (int64_t)tmax * C;
     S *s_y = reinterpret_cast<S *>(lds + align16(nv * sizeof(A)));
-    S *s_w = s_y + (int64_t)tmax * C;
     uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + lds_xs(nv, sizeof(A)));
-    int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
-                                                   align16(((int64_t)emax + 4) * 2));
-    const int tid = threadIdx.x, B = blockDim.x;
-    const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
-    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
-    const int e0 = P.iv_ptr[t], NI = P.iv_ptr[t + 1] - e0;
-    int32_t *s_ivslot = s_ivrow + NI;
-    const int W = NI ? P.iv_slot[e0 + NI - 1] + P.iv_len[e0 + NI - 1] : 0;
+    int32_t *s_iv = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
+                                                align16(((int64_t)emax + 4) * 2));
+    const int tid = threadIdx.x, B = blockDim.x, half = 2 * B;
+    const TileRec *R = P.trec + t;
+    const int r0 = R->r0, T = R->r1 - r0, k0 = R->k0, k1 = R->k1, kb = k0 & ~1;
+    const int e0 = R->e0, NI = R->ni, W = R->w;
+    const int64_t goff = R->goff;
     __syncthreads();   // the workgroup's previous use of LDS is finished
-    for (int i = tid; i < NI; i += B) {
-        s_ivrow[i] = P.iv_row[e0 + i];
-        s_ivslot[i] = P.iv_slot[e0 + i];
+    if (NI > kRecIntervals) {
+        for (int i = tid; i < NI; i += B) {
+            s_iv[i] = P.iv_row[e0 + i];
+            s_iv[NI + i] = P.iv_slot[e0 + i];
+        }
     }
-    fill_row_ids(ia, r0, r1, kb, s_rid);
-    const int half = 2 * B;
+    fill_row_ids(ia, r0, r0 + T, kb, s_rid);
+    RecWindow wm;
+    wm.init(R, s_iv);
+    __syncthreads();   // the interval list is visible to the window staging
+    const Entries<VT, false> E(ja, al, au, kb, k1);
     for (int cc = 0; cc < r; cc += C) {
         const int nc = min(C, r - cc);
-        __syncthreads();   // previous chunk's readers are done; tables are visible
-        for (int e = tid; e < T * C; e += B) {
-            const int i = e / C, c = e % C;
-            const A xv = c < nc ? (A)X[(int64_t)(r0 + i) * ldx + cc + c] : A(0);
-            s_x[e] = xv;
-            s_y[e] = (A)ldv(ad, r0 + i) * xv;
-        }
-        for (int e = tid; e < W * C; e += B) {
-            const int sl = e / C, c = e % C;
-            const int k = upper_index(s_ivslot, NI, sl);
-            s_xw[e] = c < nc ? (A)X[(int64_t)(s_ivrow[k] + (sl - s_ivslot[k])) * ldx + cc + c] : A(0);
-            s_w[e] = 0;
+        if (cc) __syncthreads();   // the previous chunk's readers are done
+        Batch<VT, true, true, false> cur;
+        cur.load(kb + 2 * tid, E);
+        // staging: U elements per thread at a time, their loads in flight
+        // together (row i < T: own row r0 + i; else window slot i - T)
+        constexpr int U = 8;
+        const int ne = (T + W) * C;
+        for (int e0 = tid; e0 < ne; e0 += U * B) {
+            A xv[U], dv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * B;
+                const int i = e / C, c = e % C;
+                xv[u] = A(0);
+                dv[u] = A(0);
+                if (e < ne) {
+                    const int row = i < T ? r0 + i : wm.row_of(i - T);
+                    if (c < nc) xv[u] = (A)X[(int64_t)row * ldx + cc + c];
+                    if (i < T) dv[u] = (A)ldv(ad, row);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * B;
+                if (e < ne) {
+                    const int i = e / C, c = e % C;
+                    s_x[c * ld + i] = xv[u];
+                    s_y[c * ld + i] = dv[u] * xv[u];
+                }
+            }
         }
         __syncthreads();
         settle_loads();
-        const Entries<VT, false> E(ja, al, au, kb, k1);
-        Batch<VT, true, true, false> cur;
-        cur.load(kb + 2 * tid, E);
-        for (int qb = kb + 2 * tid; qb < k1; qb += 2 * half) {
+        int base = kb;
+        do {
+            const int qb = base + 2 * tid;
             Batch<VT, true, true, false> nxt;
-            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, E);
-#pragma unroll
-            for (int sp = 0; sp < 2; ++sp) {
-                const int q = qb + half * sp;
-                if (q >= k1) continue;
-                const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - kb));
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int row = (int)((rv >> (16 * h)) & 0xFFFF);
-                    if (row == (int)kNoRow) continue;
-                    const int j = cur.j[sp][h];
-                    A acc[C];
-#pragma unroll
-                    for (int c = 0; c < C; ++c) acc[c] = A(0);
-                    if (j >= r0) {
-                        mm_entry<C>(cur.a[sp][h], cur.u[sp][h], s_x + row * C, s_x + (j - r0) * C,
-                                    s_y + (j - r0) * C, acc);
-                    } else {
-                        const int k = upper_index(s_ivrow, NI, j);
-                        const int sl = s_ivslot[k] + (j - s_ivrow[k]);
-                        mm_entry<C>(cur.a[sp][h], cur.u[sp][h], s_x + row * C, s_xw + sl * C, s_w + sl * C,
-                                    acc);
-                    }
-#pragma unroll
-                    for (int c = 0; c < C; ++c) atomic_add(&s_y[row * C + c], acc[c]);
-                }
-            }
+            if (base + 2 * half < k1) nxt.load(qb + 2 * half, E);
+            process_batch_mm<VT, C>(cur, qb, kb, k1, s_rid, s_x, s_y, ld, r0, T, wm, nc);
             cur = nxt;
-        }
+            base += 2 * half;
+        } while (base < k1);
         __syncthreads();
         for (int e = tid; e < T * C; e += B) {
             const int i = e / C, c = e % C;
-            if (c < nc) Y[(int64_t)(r0 + i) * ldy + cc + c] = (YT)s_y[e];
+            if (c < nc) Y[(int64_t)(r0 + i) * ldy + cc + c] = (YT)s_y[c * ld + i];
         }
         if (W) {
-            A *part = reinterpret_cast<A *>(P.partials) + P.iv_goff[e0] * r;
+            A *part = reinterpret_cast<A *>(P.partials);
             for (int e = tid; e < W * C; e += B) {
                 const int sl = e / C, c = e % C;
-                if (c < nc) part[(int64_t)sl * r + cc + c] = (A)s_w[e];
+                if (c < nc) part[(goff + sl) * r + cc + c] = (A)s_y[c * ld + T + sl];
             }
         }
     }
 }
 
 template <class VT, class YT>
-__global__ __launch_bounds__(512) void k_private_mm(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
+__global__ __launch_bounds__(512) void k_private_mm(PlanDev P, const int32_t *__restrict__ ia,
                                                     const int32_t *__restrict__ ja,
                                                     const typename VT::V *__restrict__ ad,
                                                     const typename VT::V *__restrict__ al,
                                                     const typename VT::V *__restrict__ au,
                                                     const typename VT::X *__restrict__ X, int64_t ldx,
-                                                    YT *__restrict__ Y, int64_t ldy, int r, int tmax,
-                                                    int wmax, int emax)
+                                                    YT *__restrict__ Y, int64_t ldy, int r, int smax, int emax)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    private_tile_mm<VT, YT>(P, xcd_tile(blockIdx.x, gridDim.x), kend, ia, ja, ad, al, au, X, ldx, Y, ldy, r,
-                            tmax, wmax, emax, lds);
+    private_tile_mm<VT, YT>(P, xcd_tile(blockIdx.x, gridDim.x), ia, ja, ad, al, au, X, ldx, Y, ldy, r, smax, emax,
+                            lds);
 }
 
-// Merge pass for r columns: Y[i, c] += partial slots covering row i, in
-// ascending tile order; partial slot g of a tile holds r values.
+// Merge pass for r columns: Y[i, c] += the partial slots covering row i, in
+// ascending tile order (partial slot g holds r values).  One thread per
+// (row, column), U of them per thread at a time; segments are taken K at a
+// time, so up to U K partial loads are in flight together.
 template <class A, class YT, class MT, bool COMP>
 __device__ __forceinline__ void merge_block_mm(int32_t n, const PlanDev &P, YT *__restrict__ Y, int64_t ldy,
                                                int r, int b)
 {
+    constexpr int K = 4, U = 4;
     const int e0 = P.mb_ptr[b], e1 = P.mb_ptr[b + 1];
     if (e0 == e1) return;
     const A *part = reinterpret_cast<const A *>(P.partials);
-    for (int e = threadIdx.x; e < kMergeBlock * r; e += blockDim.x) {
-        const int i = b * kMergeBlock + e / r, c = e % r;
-        if (i >= n) break;
-        MT s = (MT)Y[(int64_t)i * ldy + c], cm = MT(0);
-        for (int e = e0; e < e1; ++e) {
-            const MergeSeg g = P.mb_seg[e];
-            if (i >= g.lo && i < g.hi) {
-                const MT v = (MT)part[(g.base + i) * r + c];
-                if (COMP) {
-                    const MT s2 = s + v;
-                    const MT bp = s2 - s;
-                    cm += (s - (s2 - bp)) + (v - bp);
-                    s = s2;
-                } else {
-                    s += v;
+    const int rows = min(kMergeBlock, n - b * kMergeBlock);
+    const int ne = rows * r;
+    const int B = blockDim.x;
+    for (int f0 = threadIdx.x; f0 < ne; f0 += U * B) {
+        int i[U], c[U];
+        MT s[U], cm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int f = min(f0 + u * B, ne - 1);   // clamped lanes repeat a valid element, not stored
+            i[u] = b * kMergeBlock + f / r;
+            c[u] = f % r;
+            s[u] = (MT)Y[(int64_t)i[u] * ldy + c[u]];
+            cm[u] = MT(0);
+        }
+        for (int g0 = e0; g0 < e1; g0 += K) {
+            A v[K][U];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const MergeSeg g = P.mb_seg[min(g0 + k, e1 - 1)];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    v[k][u] = A(0);
+                    if (g0 + k < e1 && i[u] >= g.lo && i[u] < g.hi) v[k][u] = part[(g.base + i[u]) * r + c[u]];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (g0 + k >= e1) break;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const MT w = (MT)v[k][u];
+                    if (COMP) {
+                        const MT s2 = s[u] + w;
+                        const MT bp = s2 - s[u];
+                        cm[u] += (s[u] - (s2 - bp)) + (w - bp);
+                        s[u] = s2;
+                    } else {
+                        s[u] += w;
+                    }
                 }
             }
         }
-        Y[(int64_t)i * ldy + c] = (YT)(s + cm);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (f0 + u * B < ne) Y[(int64_t)i[u] * ldy + c[u]] = (YT)(s[u] + cm[u]);
     }
 }
 
@@ -1247,7 +1367,7 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge_mm(int32_t n, PlanDev P, 
 
 template <class VT, class YT>
 __global__ __launch_bounds__(512) void k_batch_tiles(const MatDev *__restrict__ mats, const int2 *__restrict__ items,
-                                                     int nitems, int transpose, int tmax, int wmax, int emax)
+                                                     int nitems, int transpose, int smax, int emax)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     using V = typename VT::V;
@@ -1256,9 +1376,9 @@ __global__ __launch_bounds__(512) void k_batch_tiles(const MatDev *__restrict__ 
         const MatDev &M = mats[w.x];
         const V *al = static_cast<const V *>(transpose ? M.au : M.al);
         const V *au = static_cast<const V *>(transpose ? M.al : M.au);
-        private_tile_mm<VT, YT>(M.P, w.y, M.k, M.ia, M.ja, static_cast<const V *>(M.ad), al, au,
+        private_tile_mm<VT, YT>(M.P, w.y, M.ia, M.ja, static_cast<const V *>(M.ad), al, au,
                                 static_cast<const typename VT::X *>(M.X), M.ldx, static_cast<YT *>(M.Y), M.ldy,
-                                M.r, tmax, wmax, emax, lds);
+                                M.r, smax, emax, lds);
     }
 }
 
@@ -1270,7 +1390,6 @@ __global__ __launch_bounds__(kMergeBlock) void k_batch_merge(const MatDev *__res
         const int2 w = items[it];
         const MatDev &M = mats[w.x];
         merge_block_mm<A, YT, MT, COMP>(M.n, M.P, static_cast<YT *>(M.Y), M.ldy, M.r, w.y);
-        __syncthreads();
     }
 }
 
@@ -1503,8 +1622,7 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         break;
     }
     case CSRC_V_PRIVATE: {
-        const int tmax = p->max_tile_rows, wmax = p->max_window, emax = p->max_tile_entries;
-        const int smax = p->max_span;
+        const int emax = p->max_tile_entries, smax = p->max_span;
         if (single) {
             const size_t lds = (size_t)lds_private(smax, emax, p->max_intervals, sizeof(Acc));
             if (p->o.persistent) {
@@ -1545,12 +1663,11 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
                     k_merge<Acc, YT, float, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y);
             }
         } else {
-            const size_t lds = (size_t)lds_private_mm(tmax, wmax, emax, p->max_intervals, sizeof(Acc),
-                                                      MmCols<VT>::C);
+            const size_t lds = (size_t)lds_private_mm(smax, emax, p->max_intervals, sizeof(Acc), MmCols<VT>::C);
             if (lds > (size_t)kLdsBudget) return CSRC_ERR_UNSUPPORTED;
             auto kern = k_private_mm<VT, YT>;
             if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
-            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, ldx, y, ldy, r, tmax, wmax, emax);
+            kern<<<p->ntiles, B, lds, s>>>(P, A->ia, A->ja, ad, al, au, x, ldx, y, ldy, r, smax, emax);
             if (p->nmerge_blocks > 0 && p->window_slots > 0) {
                 if (std::is_same<YT, double>::value)
                     k_merge_mm<Acc, YT, double, false><<<p->nmerge_blocks, kMergeBlock, 0, s>>>(n, P, y, ldy, r);
@@ -1757,9 +1874,8 @@ extern "C" int csrc_batch_run(const csrc_batch_plan *b, int32_t transpose, void 
     const MatDev *mats = reinterpret_cast<const MatDev *>(ws + b->off_descs);
     const int2 *items = reinterpret_cast<const int2 *>(ws + b->off_items);
     const int2 *mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
-    int tr = transpose ? 1 : 0, tmax = b->tmax, wmax = b->wmax, emax = b->emax;
-    void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&tmax, (void *)&wmax,
-                     (void *)&emax};
+    int tr = transpose ? 1 : 0, smax = b->smax, emax = b->emax;
+    void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&smax, (void *)&emax};
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = hip_status(hipLaunchKernel(L.tiles_fn, dim3(L.grid), dim3(L.block), args1, L.lds, s));
     if (st || nm == 0) return st;
@@ -1798,14 +1914,14 @@ extern "C" int csrc_batch_graph_create(const csrc_batch_plan *b, int32_t transpo
     const int2 *items = reinterpret_cast<const int2 *>(ws + b->off_items);
     const int2 *mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
     int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
-    int tr = transpose ? 1 : 0, tmax = b->tmax, wmax = b->wmax, emax = b->emax;
+    int tr = transpose ? 1 : 0, smax = b->smax, emax = b->emax;
     hipGraph_t g = nullptr;
     st = hip_status(hipGraphCreate(&g, 0));
     if (st) return st;
     hipGraphNode_t n1 = nullptr, n2 = nullptr;
     if (nitems > 0) {
-        void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&tmax,
-                         (void *)&wmax, (void *)&emax};
+        void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&smax,
+                         (void *)&emax};
         hipKernelNodeParams k1{};
         k1.func = const_cast<void *>(L.tiles_fn);
         k1.gridDim = dim3(L.grid);

@@ -55,10 +55,13 @@ inline int64_t lds_atomic(int64_t tmax, int64_t emax, int acc)
 {
     return lds_xs(tmax, acc) + align16((emax + 4) * 2);
 }
-// multi-column forms: C columns of each per-row and per-slot array
-inline int64_t lds_private_mm(int64_t tmax, int64_t wmax, int64_t emax, int64_t ivmax, int acc, int C)
+// multi-column forms: C columns of each per-row and per-slot array.  PRIVATE
+// keeps them column-major with leading dimension mm_ld(smax), which is 1 mod
+// 32 so that the C values of one row fall into different LDS banks.
+constexpr int mm_ld(int64_t smax) { return (int)(((smax + 31) & ~int64_t(31)) + 1); }
+inline int64_t lds_private_mm(int64_t smax, int64_t emax, int64_t ivmax, int acc, int C)
 {
-    return lds_xs((tmax + wmax) * C, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+    return lds_xs((int64_t)mm_ld(smax) * C, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
 inline int64_t lds_owner_mm(int64_t tmax, int64_t pmax, int64_t emax, int acc, int C)
 {
@@ -187,7 +190,7 @@ struct csrc_batch_plan {
     std::vector<int64_t> part_off;   // partial slots of matrix m (bytes, from off_parts)
     std::vector<int32_t> items;      // (matrix, tile) pairs, decreasing cost
     std::vector<int32_t> mitems;     // (matrix, merge block) pairs
-    int32_t tmax = 0, wmax = 0, emax = 0, ivmax = 0;
+    int32_t smax = 0, emax = 0, ivmax = 0;   // largest rows + slots, entries, intervals of a tile
     int64_t lds = 0;
     std::vector<char> blob;          // tables + work lists (uploaded by bind)
     int64_t off_items = 0, off_mitems = 0, off_descs = 0, off_parts = 0, ws_bytes = 0;
