@@ -148,6 +148,26 @@ def measured_traffic(workload, dtype, vname, vkw):
     return None
 
 
+def hbm_ceiling(torch, nbytes=2 * 2**30, reps=5):
+    """Measured ceiling: a plain device copy of nbytes, GB/s of bytes read plus
+    written (outside every timed region)."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(gbs, 1), "kind": f"device copy of {nbytes >> 20} MiB, bytes read + written"}
+
+
 def cpu_baseline(host, x, budget_s=12.0):
     """Oracle (plain sequential C, 1 thread) on the same matrix: y=Ax, y=A^T x."""
     from oracle import reference as R
@@ -283,6 +303,8 @@ def bench_batch(args):
 
     gbs = 2 * B1 / (ms * 1e-3) / 1e9
     ach = gbs
+    ceiling = hbm_ceiling(torch)
+    ceiling["value_frac_of_ceiling"] = round(gbs / ceiling["copy_gbs"], 4)
     out = {
         "metric": METRIC,
         "value": round(gbs, 1),
@@ -303,6 +325,7 @@ def bench_batch(args):
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "max_rel_err_vs_oracle": err,
         "parity_sample": sample,
+        "hbm_ceiling": ceiling,
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
@@ -454,6 +477,8 @@ def main():
                "gflops": round(2 * flops(n, k) / dt / 1e9, 3)}
 
     ach = B1 / (per_prod_ms * 1e-3) / 1e9
+    ceiling = hbm_ceiling(torch)
+    ceiling["value_frac_of_ceiling"] = round(gbs / ceiling["copy_gbs"], 4)
     if vname == "private":
         launches = ("one product = k_fill_zero + k_private (atomic merge)" if vkw.get("atomic_merge")
                     else "one product = k_private + k_merge")
@@ -481,6 +506,7 @@ def main():
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "us_per_product": {"Ax": round(fwd * 1e3, 2), "ATx": round(bwd * 1e3, 2)},
         "max_rel_err_vs_oracle": float(err),
+        "hbm_ceiling": ceiling,
         "plain_fp64": plain,
         "speedup_vs_plain": round(plain["ms_per_step"] / ms, 3) if plain else None,
         "selection": selection,
