@@ -283,6 +283,69 @@ __device__ __forceinline__ void settle_loads() { __builtin_amdgcn_s_waitcnt(0); 
 // them).  The batch loop runs the same number of times in every lane (lanes
 // past k1 see only kNoRow), so after_first() is called once, by all lanes
 // together, after the first batch.
+// Lane exchange inside groups of 4 and 8 lanes (DPP: quad permutation and
+// half-row mirror), for 32- and 64-bit values.  Every lane of the wave must
+// be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(dpp<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const i2v p = __builtin_bit_cast(i2v, v);
+    i2v q;
+    q.x = dpp<CTRL>(p.x);
+    q.y = dpp<CTRL>(p.y);
+    return __builtin_bit_cast(double, q);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within each group of 8
+
+// Flush a lane's pair of gathered products (rows r0 <= r1 of its two
+// entries, kNoRow for none).  Consecutive lanes often hold pairs of one long
+// row, and their LDS adds to one address are serialised; so the pair sums of
+// a row segment are first reduced across lanes: when all 8 (else all 4)
+// lanes of an aligned group hold one pair of the same row, the group's first
+// lane adds the group's total.  Called by every lane of the wave.
+template <class A, class Flush>
+__device__ __forceinline__ void flush_pairs(int r0, int r1, A g0, A g1, Flush flush)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const bool one = r0 == r1 && r0 != (int)kNoRow;
+    const int key = one ? r0 : -1 - lane;          // distinct for lanes that do not take part
+    const A v = g0 + g1;
+    // every exchange is evaluated by all lanes before any branch (a lane
+    // exchange under a partial exec mask reads undefined values): no
+    // short-circuit operators here
+    const int k1 = dpp<kDppXor1>(key), k2 = dpp<kDppXor2>(key);
+    const int k3 = dpp<kDppXor1>(k2);
+    const bool quad = (key == k1) & (key == k2) & (key == k3);
+    A vq = v + dpp<kDppXor1>(v);
+    vq = vq + dpp<kDppXor2>(vq);
+    const int kq = quad ? key : -1 - (lane | 64);   // a quad's key when the whole quad is one row
+    const int km = dpp<kDppHalfMirror>(kq);
+    const bool oct = quad & (kq == km);
+    const A vo = vq + dpp<kDppHalfMirror>(vq);
+    if (oct) {
+        if ((lane & 7) == 0) flush(r0, vo);
+    } else if (quad) {
+        if ((lane & 3) == 0) flush(r0, vq);
+    } else if (one) {
+        flush(r0, v);
+    } else {
+        if (r0 != (int)kNoRow) flush(r0, g0);
+        if (r1 != (int)kNoRow) flush(r1, g1);
+    }
+}
+
 // Process one batch held in cur (lane pairs at qb and qb + 2B of the
 // entries E): for each entry of row r (relative) with column j,
 // x_j = ent(j, au * s_x[r]) scatters and gathers, and a lane's run of
@@ -326,12 +389,7 @@ __device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT> &cur,
         A g0 = A(0), g1 = A(0);
         if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * xr[s][0]);
         if (r1 != (int)kNoRow) g1 = cur.a[s][1] * ent(cur.j[s][1], cur.u[s][1] * xr[s][1]);
-        if (r0 == r1) {
-            if (r0 != (int)kNoRow) flush(r0, g0 + g1);
-        } else {
-            if (r0 != (int)kNoRow) flush(r0, g0);
-            if (r1 != (int)kNoRow) flush(r1, g1);
-        }
+        flush_pairs(r0, r1, g0, g1, flush);
     }
 }
 
