@@ -37,9 +37,11 @@ HBM_PEAK_GBS = 8000.0
 MALL_BYTES = 256 * 2**20
 
 
-def algorithmic_bytes(n, k, vbytes, xbytes, ybytes, r=1):
-    """Bytes one product must move: every array once (paper's working set)."""
-    return 4 * (n + 1) + k * (4 + 2 * vbytes) + n * vbytes + r * n * (xbytes + ybytes)
+def algorithmic_bytes(n, k, vbytes, xbytes, ybytes, r=1, symmetric=False):
+    """Bytes one product must move: every array once (paper's working set);
+    numerically symmetric storage holds one value array (Sec. 2.2)."""
+    nv = 1 if symmetric else 2
+    return 4 * (n + 1) + k * (4 + nv * vbytes) + n * vbytes + r * n * (xbytes + ybytes)
 
 
 def flops(n, k, r=1):
@@ -55,6 +57,8 @@ def build_workload(name):
         return W.hex_mesh(100, "random")
     if name == "hex100_rcm":
         return W.hex_mesh(100, "rcm")
+    if name == "hex100_sym":
+        return W.hex_mesh(100, "natural", kind="sym")
     if name.startswith("hex"):
         return W.hex_mesh(int(name[3:]), "natural")
     if name == "tet80":
@@ -65,8 +69,8 @@ def build_workload(name):
 class Copies:
     """Independent device copies of (A, x, y, y_t) for cache-cold rotation."""
 
-    def __init__(self, C, torch, host, dtype, ncopy, x):
-        self.mats = [C.Matrix(host, dtype) for _ in range(ncopy)]
+    def __init__(self, C, torch, host, dtype, ncopy, x, symmetric=False):
+        self.mats = [C.Matrix(host, dtype, symmetric=symmetric) for _ in range(ncopy)]
         xd = self.mats[0].xdtype
         self.x = [torch.from_numpy(x).to("cuda", xd) for _ in range(ncopy)]
         self.y = []
@@ -382,9 +386,10 @@ def main():
     vb = {"f64": 8, "f32": 4, "bf16": 2}[args.dtype]
     xb = 8 if args.dtype == "f64" else 4
     yb = xb
-    B1 = algorithmic_bytes(n, k, vb, xb, yb)
+    sym = args.workload.endswith("_sym")
+    B1 = algorithmic_bytes(n, k, vb, xb, yb, symmetric=sym)
     ncopy = args.copies or max(2, math.ceil(3 * MALL_BYTES / B1))
-    cp = Copies(C, torch, host, args.dtype, ncopy, x)
+    cp = Copies(C, torch, host, args.dtype, ncopy, x, symmetric=sym)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s n={n} k={k} bytes/product={B1} copies={ncopy}",
           file=sys.stderr, flush=True)
 

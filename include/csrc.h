@@ -113,7 +113,11 @@ int csrc_quantize(int64_t count, const double *src, int32_t dtype, void *dst);
 
 /* A CSRC matrix resident on the device.  Value arrays hold vdtype.  ja, al
  * and au must be 16-byte aligned (8-byte for BF16 values), as hipMalloc'd
- * memory is: the kernels read them with vector loads (CSRC_ERR_ARG if not). */
+ * memory is: the kernels read them with vector loads (CSRC_ERR_ARG if not).
+ * Numerically symmetric storage (Sec. 2.2: a_ji = a_ij, so au equals al and
+ * is not stored): pass au == al.  Every product then equals its transpose;
+ * the PRIVATE single-vector kernels read al once per entry instead of two
+ * value arrays, and the other kernels read the one array twice. */
 typedef struct csrc_matrix {
     int32_t n;
     int32_t vdtype;        /* csrc_dtype of ad, al, au                        */

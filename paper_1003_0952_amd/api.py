@@ -91,10 +91,12 @@ class Matrix:
 
     ``host`` is the dict of csrc_from_csr; values are stored as ``dtype``
     ("f64", "f32" or "bf16"; rounded by csrc_quantize).  The host structure
-    (ia, ja) is kept for plan creation.
+    (ia, ja) is kept for plan creation.  ``symmetric=True`` stores a
+    numerically symmetric matrix (au equal to al, checked) once: the
+    descriptor's au is al.
     """
 
-    def __init__(self, host, dtype="f64", device="cuda"):
+    def __init__(self, host, dtype="f64", device="cuda", symmetric=False):
         import torch
         self.n = int(host["n"])
         self.k = int(host["k"])
@@ -107,7 +109,13 @@ class Matrix:
         self.ja = t(self.host_ja)
         self.ad = t(csrc_quantize(host["ad"], self.vdtype))
         self.al = t(csrc_quantize(host["al"], self.vdtype))
-        self.au = t(csrc_quantize(host["au"], self.vdtype))
+        self.symmetric = bool(symmetric)
+        if self.symmetric:
+            if not np.array_equal(host["al"], host["au"]):
+                raise ValueError("symmetric=True needs au equal to al")
+            self.au = self.al
+        else:
+            self.au = t(csrc_quantize(host["au"], self.vdtype))
         self.desc = B.CsrcMatrix(self.n, self.vdtype, self.k, t_ptr(self.ia).value or 0,
                                  t_ptr(self.ja).value or 0, t_ptr(self.ad).value or 0,
                                  t_ptr(self.al).value or 0, t_ptr(self.au).value or 0)
@@ -119,7 +127,8 @@ class Matrix:
 
     def nbytes(self):
         vb = {B.F64: 8, B.F32_: 4, B.BF16: 2}[self.vdtype]
-        return 4 * (self.n + 1) + self.k * (4 + 2 * vb) + self.n * vb
+        nv = 1 if self.symmetric else 2
+        return 4 * (self.n + 1) + self.k * (4 + nv * vb) + self.n * vb
 
 
 class Plan:

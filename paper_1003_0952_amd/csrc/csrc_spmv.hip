@@ -257,8 +257,15 @@ struct Batch {
             E.j2(q, j[s]);
             if (LOAD_AL) E.al2(q, a[s]);
             else a[s][0] = a[s][1] = A(0);
-            if (LOAD_AU) E.au2(q, u[s]);
-            else u[s][0] = u[s][1] = A(0);
+            if constexpr (VT::kSym) {
+                static_assert(LOAD_AL && LOAD_AU, "symmetric storage loads al for both");
+                u[s][0] = a[s][0];
+                u[s][1] = a[s][1];
+            } else if (LOAD_AU) {
+                E.au2(q, u[s]);
+            } else {
+                u[s][0] = u[s][1] = A(0);
+            }
         }
     }
 };
@@ -1703,12 +1710,13 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
                                                                      p->max_span_padded, emax, buf);
             } else if (p->o.atomic_merge) {
                 k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
-                auto kern = k_private<VT, YT, true>;
+                // numerically symmetric storage (au is al): one value load per entry
+                auto kern = al == au ? k_private<SymT<VT>, YT, true> : k_private<VT, YT, true>;
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
                 kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
                 return hip_status(hipGetLastError());
             } else {
-                auto kern = k_private<VT, YT, false>;
+                auto kern = al == au ? k_private<SymT<VT>, YT, false> : k_private<VT, YT, false>;
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
                 kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
             }

@@ -15,9 +15,13 @@ namespace csrc {
 // Products, row sums, partials and the merge use A; only the LDS sums are
 // FP64 for every storage type, because the LDS of gfx950 executes ds_add_f64
 // at about twenty times the rate of ds_add_f32.
-struct F64T { using V = double;   using X = double; using A = double; using S = double; };
-struct F32T { using V = float;    using X = float;  using A = float;  using S = double; };
-struct B16T { using V = uint16_t; using X = float;  using A = float;  using S = double; };
+struct F64T { using V = double;   using X = double; using A = double; using S = double; static constexpr bool kSym = false; };
+struct F32T { using V = float;    using X = float;  using A = float;  using S = double; static constexpr bool kSym = false; };
+struct B16T { using V = uint16_t; using X = float;  using A = float;  using S = double; static constexpr bool kSym = false; };
+// Numerically symmetric storage of a value type: au is al, so the value of
+// an entry is loaded once and serves both the gather and the scatter.
+template <class Base>
+struct SymT : Base { static constexpr bool kSym = true; };
 
 __device__ __forceinline__ double ldv(const double *p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const float *p, int64_t i) { return p[i]; }

@@ -190,3 +190,19 @@ def test_flop_and_load_model():
     loads = 2.5 * nnz - 0.5 * n
     assert abs(loads / flops - 1.26) < 0.02
     assert 3 * nnz / (2 * nnz) == 1.5
+
+
+@pytest.mark.parametrize("name", ["quad64", "hex12_random", "tet5x3"])
+def test_numerically_symmetric_storage(name):
+    """Sec. 2.2: for a numerically symmetric matrix the CSRC split gives
+    au equal to al, A x equals A^T x, and both equal scipy's product."""
+    make = {"quad64": lambda: W.quad64(kind="sym"), "hex12_random": lambda: W.hex_mesh(12, "random", kind="sym"),
+            "tet5x3": lambda: W.tet_mesh(5, kind="sym")}[name]
+    a, x = make()
+    A = scipy_A(a)
+    assert abs(A - A.T).max() == 0.0
+    c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+    assert np.array_equal(c["al"], c["au"])
+    y = R.spmv(c, x)
+    assert np.array_equal(y, R.spmv_t(c, x))
+    assert rel_inf(y, A @ x) <= 1e-14
