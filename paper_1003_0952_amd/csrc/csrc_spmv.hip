@@ -237,22 +237,24 @@ __device__ __forceinline__ void fill_row_ids(const int32_t *__restrict__ ia, int
     }
 }
 
-// One lane's share of a batch: pairs at qb and qb + 2B of the entries E.
-// LOAD_AL / LOAD_AU select which value arrays are fetched up front (the
-// others read as zero).  Pairs past the range of E read as zero.
-template <class VT, bool LOAD_AL, bool LOAD_AU, bool NT>
+// One lane's share of a batch: NP pairs at qb, qb + 2B, ... of the entries
+// E (a batch covers 2 NP B consecutive entries).  LOAD_AL / LOAD_AU select
+// which value arrays are fetched up front (the others read as zero).  Pairs
+// past the range of E read as zero.
+template <class VT, bool LOAD_AL, bool LOAD_AU, bool NT, int NP = 2>
 struct Batch {
     using A = typename VT::A;
     using V = typename VT::V;
-    int j[2][2];
-    A a[2][2];
-    A u[2][2];
+    static constexpr int kPairs = NP;
+    int j[NP][2];
+    A a[NP][2];
+    A u[NP][2];
 
     __device__ __forceinline__ void load(int qb, const Entries<VT, NT> &E)
     {
         const int half = 2 * (int)blockDim.x;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < NP; ++s) {
             const int q = qb + half * s;
             E.j2(q, j[s]);
             if (LOAD_AL) E.al2(q, a[s]);
@@ -353,29 +355,29 @@ __device__ __forceinline__ void flush_pairs(int r0, int r1, A g0, A g1, Flush fl
     }
 }
 
-// Process one batch held in cur (lane pairs at qb and qb + 2B of the
+// Process one batch held in cur (lane pairs at qb, qb + 2B, ... of the
 // entries E): for each entry of row r (relative) with column j,
 // x_j = ent(j, au * s_x[r]) scatters and gathers, and a lane's run of
 // gathered products of one row goes to flush(r, sum).  With LOAD_AU false,
 // an au pair is fetched only if need_au(j) holds for one of its entries
 // (else its products are zero and ent ignores them).
-template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush>
-__device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT> &cur, int qb, const Entries<VT, NT> &E,
-                                              const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
-                                              NeedAu need_au, Ent ent, Flush flush)
+template <class VT, bool LOAD_AU, bool NT, int NP, class NeedAu, class Ent, class Flush>
+__device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT, NP> &cur, int qb,
+                                              const Entries<VT, NT> &E, const uint16_t *__restrict__ s_rid,
+                                              const typename VT::A *s_x, NeedAu need_au, Ent ent, Flush flush)
 {
     using A = typename VT::A;
     const int half = 2 * (int)blockDim.x;
     const int kb = E.kb, k1 = E.ke;
-    uint32_t rv[2];
+    uint32_t rv[NP];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NP; ++s) {
         const int q = qb + half * s;
         rv[s] = q < k1 ? *reinterpret_cast<const uint32_t *>(s_rid + (q - kb)) : 0xFFFFFFFFu;
     }
     if (!LOAD_AU) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < NP; ++s) {
             const bool need = ((rv[s] & 0xFFFF) != kNoRow && need_au(cur.j[s][0])) ||
                               ((rv[s] >> 16) != kNoRow && need_au(cur.j[s][1]));
             if (need) E.au2(qb + half * s, cur.u[s]);
@@ -383,15 +385,15 @@ __device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT> &cur,
         }
     }
     // x of the entries' own rows, read before any LDS update of the batch
-    A xr[2][2];
+    A xr[NP][2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NP; ++s) {
         const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
         xr[s][0] = s_x[r0 != (int)kNoRow ? r0 : 0];
         xr[s][1] = s_x[r1 != (int)kNoRow ? r1 : 0];
     }
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NP; ++s) {
         const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
         A g0 = A(0), g1 = A(0);
         if (r0 != (int)kNoRow) g0 = cur.a[s][0] * ent(cur.j[s][0], cur.u[s][0] * xr[s][0]);
@@ -405,8 +407,8 @@ __device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT> &cur,
 // processed while the next one loads.  The batch loop runs the same number
 // of times in every lane (lanes past k1 see only kNoRow), so after_first()
 // is called once, by all lanes together, after the first batch.
-template <class VT, bool LOAD_AU, bool NT, class NeedAu, class Ent, class Flush, class Hook = NoHook>
-__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, const Entries<VT, NT> &E,
+template <class VT, bool LOAD_AU, bool NT, int NP, class NeedAu, class Ent, class Flush, class Hook = NoHook>
+__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT, NP> &cur, const Entries<VT, NT> &E,
                                            const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
                                            NeedAu need_au, Ent ent, Flush flush, Hook after_first = Hook())
 {
@@ -415,12 +417,12 @@ __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT> &cur, co
     int base = kb;
     do {
         const int qb = base + 2 * (int)threadIdx.x;
-        Batch<VT, true, LOAD_AU, NT> nxt;
-        if (base + 2 * half < k1) nxt.load(qb + 2 * half, E);
+        Batch<VT, true, LOAD_AU, NT, NP> nxt;
+        if (base + NP * half < k1) nxt.load(qb + NP * half, E);
         process_batch<VT, LOAD_AU, NT>(cur, qb, E, s_rid, s_x, need_au, ent, flush);
         if (base == kb) after_first();
         cur = nxt;
-        base += 2 * half;
+        base += NP * half;
     } while (base < k1);
 }
 
@@ -678,6 +680,12 @@ struct WindowMap {
 // staging loads and the first batch of entries are in flight together.
 // AM (atomic merge): y is zero beforehand and both the own rows and the
 // window slots are added to y with global atomics; no partials, no pass.
+// Pairs per lane in one batch of the PRIVATE stream.  Three or four pairs
+// put more bytes in flight per wave but cost registers (89 and 115 VGPRs for
+// FP64 against 63) and measured slower on the 27-point and tetrahedral
+// meshes, so two.
+constexpr int kPrivatePairs = 2;
+
 template <class VT, class YT, bool AM>
 __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
@@ -705,7 +713,7 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     A *s_xw = s_x + nt.T;
     S *s_w = s_y + nt.T;
     const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
-    Batch<VT, true, true, true> first;
+    Batch<VT, true, true, true, kPrivatePairs> first;
     first.load(nt.kb + 2 * tid, E);
     nt.window(x);
     nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
