@@ -356,6 +356,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-pair", action="store_true", help="skip timing csrc_spmv_pair")
     ap.add_argument("--copies", type=int, default=0)
     ap.add_argument("--tune-steps", type=int, default=30)
     args = ap.parse_args()
@@ -461,17 +462,47 @@ def main():
                  "gflops": round(2 * flops(n, k) / (pms * 1e-3) / 1e9, 1),
                  "pct_hbm_peak": round(100 * 2 * B1 / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)}
 
-    # parity spot check of the timed configuration against the oracle
+    # both products in one call (one pass over the entries when the plan is
+    # PRIVATE with the atomic merge): time per pair against the step
+    pair = None
+    if not args.no_pair:
+        nc = len(cp.mats)
+        for s_ in range(3):
+            C.csrc_spmv_pair(cp.mats[s_ % nc], plan, cp.x[s_ % nc], cp.y[s_ % nc], cp.yt[s_ % nc])
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        cnt = min(args.steps, 100)
+        t0.record()
+        for s_ in range(cnt):
+            C.csrc_spmv_pair(cp.mats[s_ % nc], plan, cp.x[s_ % nc], cp.y[s_ % nc], cp.yt[s_ % nc])
+        t1.record()
+        torch.cuda.synchronize()
+        pms_pair = t0.elapsed_time(t1) / cnt
+        Bp = algorithmic_bytes(n, k, vb, xb, yb, symmetric=sym) + n * yb   # one more output vector
+        pair = {"fused": bool(vname == "private" and vkw.get("atomic_merge")), "us_per_pair": round(pms_pair * 1e3, 2),
+                "speedup_vs_two_products": round(ms / pms_pair, 3),
+                "gbs": round(Bp / (pms_pair * 1e-3) / 1e9, 1), "bytes_per_pair": Bp}
+
+    # parity spot check of the timed configuration against the oracle (and of
+    # the pair call, when timed)
     from oracle import reference as R
     c0 = {kk: host[kk] for kk in ("n", "k", "ia", "ja", "ad", "al", "au")}
+    ry = R.spmv(c0, x)
+    ryt = R.spmv_t(c0, x)
+
+    def rel(a_, b_):
+        return float(np.max(np.abs(a_ - b_)) / np.max(np.abs(b_)))
+
     C.csrc_spmv(cp.mats[0], plan, cp.x[0], cp.y[0])
     C.csrc_spmv_t(cp.mats[0], plan, cp.x[0], cp.yt[0])
     torch.cuda.synchronize()
-    y = cp.y[0].double().cpu().numpy()
-    yt = cp.yt[0].double().cpu().numpy()
-    ry = R.spmv(c0, x)
-    ryt = R.spmv_t(c0, x)
-    err = max(np.max(np.abs(y - ry)) / np.max(np.abs(ry)), np.max(np.abs(yt - ryt)) / np.max(np.abs(ryt)))
+    err = max(rel(cp.y[0].double().cpu().numpy(), ry), rel(cp.yt[0].double().cpu().numpy(), ryt))
+    if pair is not None:
+        C.csrc_spmv_pair(cp.mats[0], plan, cp.x[0], cp.y[0], cp.yt[0])
+        torch.cuda.synchronize()
+        pair["max_rel_err_vs_oracle"] = max(rel(cp.y[0].double().cpu().numpy(), ry),
+                                            rel(cp.yt[0].double().cpu().numpy(), ryt))
 
     cpu = None
     if not args.no_cpu:
@@ -512,6 +543,7 @@ def main():
         "us_per_product": {"Ax": round(fwd * 1e3, 2), "ATx": round(bwd * 1e3, 2)},
         "max_rel_err_vs_oracle": float(err),
         "hbm_ceiling": ceiling,
+        "pair": pair,
         "plain_fp64": plain,
         "speedup_vs_plain": round(plain["ms_per_step"] / ms, 3) if plain else None,
         "selection": selection,

@@ -276,6 +276,19 @@ int csrc_spmv_t(const csrc_matrix *A, const csrc_plan *plan, const void *x,
                 void *y, void *workspace, int64_t ws_bytes, void *stream);
 
 /*
+ * csrc_spmv_pair -- y <- A x and yt <- A^T x together (Sec. 5: the transpose
+ * is the same loop with al and au exchanged; methods of the BiCG family need
+ * both).  With a PRIVATE plan using the atomic merge (not persistent) one
+ * pass reads ja, al and au once for both products; with any other plan, or
+ * when the two sum arrays exceed the LDS, the two products run one after
+ * the other.  x, y and yt are device vectors of n values (types as for
+ * csrc_spmv) and must not overlap (CSRC_ERR_ALIAS).  Asynchronous on the
+ * stream; errors as for csrc_spmv.
+ */
+int csrc_spmv_pair(const csrc_matrix *A, const csrc_plan *plan, const void *x,
+                   void *y, void *yt, void *workspace, int64_t ws_bytes, void *stream);
+
+/*
  * csrc_spmm / csrc_spmm_t -- Y <- A X (or A^T X) for r right-hand sides.
  * X and Y are row-major n x r blocks with leading dimensions ldx, ldy >= r
  * (element (i, c) at X[i*ldx + c]); 1 <= r <= plan max_rhs and r <= 32.

@@ -206,6 +206,14 @@ def csrc_spmv_t(A, plan, x, y, stream=None):
     return y
 
 
+def csrc_spmv_pair(A, plan, x, y, yt, stream=None):
+    """y <- A x and yt <- A^T x (one pass over the entries with a PRIVATE
+    atomic-merge plan).  Asynchronous on the stream."""
+    check(B.lib.csrc_spmv_pair(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y), t_ptr(yt),
+                               t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_pair")
+    return y, yt
+
+
 def csrc_spmm(A, plan, X, Y, stream=None):
     """Y <- A X for row-major n x r blocks (torch 2-D tensors, row stride = ld)."""
     r = X.shape[1]

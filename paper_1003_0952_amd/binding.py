@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libcsrc.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"libcsrc.so not found at {LIB_PATH}: build it with "
-        "`python -m paper_1003_0952_amd.build` (hipcc, gfx950)")
+        "`python paper_1003_0952_amd/build.py` (hipcc, gfx950)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -120,6 +120,7 @@ _sig("csrc_plan_get_info", ctypes.c_int, [P, P])
 _sig("csrc_plan_export", ctypes.c_int, [P, I32, P, I64, P])
 _sig("csrc_spmv", ctypes.c_int, [P, P, P, P, P, I64, P])
 _sig("csrc_spmv_t", ctypes.c_int, [P, P, P, P, P, I64, P])
+_sig("csrc_spmv_pair", ctypes.c_int, [P, P, P, P, P, P, I64, P])
 _sig("csrc_spmm", ctypes.c_int, [P, P, I32, P, I64, P, I64, P, I64, P])
 _sig("csrc_spmm_t", ctypes.c_int, [P, P, I32, P, I64, P, I64, P, I64, P])
 _sig("csrc_batch_plan_create", ctypes.c_int, [I32, P, P, P, P, I32, P, P])

@@ -748,6 +748,128 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     }
 }
 
+// ------------------------------------------------- PRIVATE, both products
+
+// y = A x and yt = A^T x in one pass over the entries.  The transpose
+// product is the same loop with al and au exchanged (Sec. 5), so per entry
+// (i, j): y_i += al x_j, y_j += au x_i, yt_i += au x_j and yt_j += al x_i.
+// One batch: ent2(j, wy, wt) scatters wy into the sums of y and wt into
+// those of yt at column j and returns x_j; the gathered products go to
+// flush_y and flush_t.
+template <class VT, class Ent2, class FlushY, class FlushT>
+__device__ __forceinline__ void process_batch_pair(Batch<VT, true, true, true> &cur, int qb,
+                                                   const Entries<VT, true> &E, const uint16_t *__restrict__ s_rid,
+                                                   const typename VT::A *s_x, Ent2 ent2, FlushY flush_y,
+                                                   FlushT flush_t)
+{
+    using A = typename VT::A;
+    const int half = 2 * (int)blockDim.x;
+    const int kb = E.kb, k1 = E.ke;
+    uint32_t rv[2];
+    A xr[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int q = qb + half * s;
+        rv[s] = q < k1 ? *reinterpret_cast<const uint32_t *>(s_rid + (q - kb)) : 0xFFFFFFFFu;
+        const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
+        xr[s][0] = s_x[r0 != (int)kNoRow ? r0 : 0];
+        xr[s][1] = s_x[r1 != (int)kNoRow ? r1 : 0];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int r0 = (int)(rv[s] & 0xFFFF), r1 = (int)(rv[s] >> 16);
+        A gy0 = A(0), gy1 = A(0), gt0 = A(0), gt1 = A(0);
+        if (r0 != (int)kNoRow) {
+            const A xj = ent2(cur.j[s][0], cur.u[s][0] * xr[s][0], cur.a[s][0] * xr[s][0]);
+            gy0 = cur.a[s][0] * xj;
+            gt0 = cur.u[s][0] * xj;
+        }
+        if (r1 != (int)kNoRow) {
+            const A xj = ent2(cur.j[s][1], cur.u[s][1] * xr[s][1], cur.a[s][1] * xr[s][1]);
+            gy1 = cur.a[s][1] * xj;
+            gt1 = cur.u[s][1] * xj;
+        }
+        flush_pairs(r0, r1, gy0, gy1, flush_y);
+        flush_pairs(r0, r1, gt0, gt1, flush_t);
+    }
+}
+
+// PRIVATE tile producing both products (atomic merge: y and yt are cleared
+// beforehand; every tile adds its own rows and window sums to both with
+// global atomics).  LDS: x of own rows then window slots, the sums of y and
+// of yt likewise, row ids, interval list.
+template <class VT, class YT>
+__global__ __launch_bounds__(512) void k_private_pair(PlanDev P, const int32_t *__restrict__ ia,
+                                                      const int32_t *__restrict__ ja,
+                                                      const typename VT::V *__restrict__ ad,
+                                                      const typename VT::V *__restrict__ al,
+                                                      const typename VT::V *__restrict__ au,
+                                                      const typename VT::X *__restrict__ x, YT *__restrict__ y,
+                                                      YT *__restrict__ yt, int smax, int emax)
+{
+    using A = typename VT::A;
+    using S = typename VT::S;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int64_t sbytes = align16((int64_t)smax * sizeof(S));
+    A *s_x = reinterpret_cast<A *>(lds);
+    S *s_y = reinterpret_cast<S *>(lds + align16((int64_t)smax * sizeof(A)));
+    S *s_t = reinterpret_cast<S *>(lds + align16((int64_t)smax * sizeof(A)) + sbytes);
+    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + lds_xs(smax, sizeof(A)) + sbytes);
+    int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
+                                                   align16(((int64_t)emax + 4) * 2));
+    const int tid = threadIdx.x, B = blockDim.x, half = 2 * B;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    NextTile<VT, 2> nt;
+    nt.issue(P, t, ia, ad, x);
+    A *s_xw = s_x + nt.T;
+    S *s_w = s_y + nt.T;
+    const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
+    Batch<VT, true, true, true> cur;
+    cur.load(nt.kb + 2 * tid, E);
+    nt.window(x);
+    nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
+    const int r0 = nt.r0, T = nt.T, W = nt.W, k1 = nt.k1;
+    WindowMap wm;
+    wm.init(nt, s_ivrow);
+    __syncthreads();
+    // the transpose has the same diagonal: its sums start as those of y
+    for (int i = tid; i < T + W; i += B) s_t[i] = s_y[i];
+    __syncthreads();
+    settle_loads();
+
+    auto ent2 = [&, wm](int j, A wy, A wt) -> A {
+        const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
+        atomic_add(&s_y[idx], wy);
+        atomic_add(&s_t[idx], wt);
+        return s_x[idx];
+    };
+    auto flush_y = [&](int r, A v) { atomic_add(&s_y[r], v); };
+    auto flush_t = [&](int r, A v) { atomic_add(&s_t[r], v); };
+    int base = nt.kb;
+    do {
+        const int qb = base + 2 * tid;
+        Batch<VT, true, true, true> nxt;
+        if (base + 2 * half < k1) nxt.load(qb + 2 * half, E);
+        process_batch_pair<VT>(cur, qb, E, s_rid, s_x, ent2, flush_y, flush_t);
+        cur = nxt;
+        base += 2 * half;
+    } while (base < k1);
+    __syncthreads();
+
+    for (int i = tid; i < T; i += B) {
+        atomic_add(&y[r0 + i], (YT)s_y[i]);
+        atomic_add(&yt[r0 + i], (YT)s_t[i]);
+    }
+    for (int b0 = 0; b0 < W; b0 += B) {
+        const int sl = b0 + tid;
+        const int row = nt.window_row(sl);   // every lane takes part
+        if (sl < W) {
+            atomic_add(&y[row], (YT)s_w[sl]);
+            atomic_add(&yt[row], (YT)s_t[T + sl]);
+        }
+    }
+}
+
 // ----------------------------------------------------- PRIVATE, persistent
 
 // PRIVATE with persistent workgroups.  XCD x (workgroups b = x mod 8) owns
@@ -1876,6 +1998,65 @@ extern "C" int csrc_spmm_t(const csrc_matrix *A, const csrc_plan *plan, int32_t 
                            void *Y, int64_t ldy, void *workspace, int64_t ws_bytes, void *stream)
 {
     return csrc::product(A, plan, r, X, ldx, Y, ldy, workspace, ws_bytes, stream, true);
+}
+
+namespace csrc {
+
+template <class VT, class YT>
+static int launch_pair(const csrc_plan *p, const csrc_matrix *A, const void *x_, void *y_, void *yt_, void *ws,
+                       hipStream_t s)
+{
+    using V = typename VT::V;
+    const int32_t n = A->n;
+    const int emax = p->max_tile_entries, smax = p->max_span;
+    const size_t lds = (size_t)lds_private_pair(smax, emax, p->max_intervals, sizeof(typename VT::A));
+    PlanDev P = plan_dev(p, ws);
+    YT *y = static_cast<YT *>(y_);
+    YT *yt = static_cast<YT *>(yt_);
+    auto kern = k_private_pair<VT, YT>;
+    if (lds > 65536 && hip_status(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      (int)lds)))
+        return CSRC_ERR_HIP;
+    k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
+    k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(yt, n, 1, 1);
+    kern<<<p->ntiles, p->o.block, lds, s>>>(P, A->ia, A->ja, static_cast<const V *>(A->ad),
+                                            static_cast<const V *>(A->al), static_cast<const V *>(A->au),
+                                            static_cast<const typename VT::X *>(x_), y, yt, smax, emax);
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace csrc
+
+extern "C" int csrc_spmv_pair(const csrc_matrix *A, const csrc_plan *plan, const void *x, void *y, void *yt,
+                              void *workspace, int64_t ws_bytes, void *stream)
+{
+    using namespace csrc;
+    int st = check_call(A, plan, workspace, ws_bytes);
+    if (st) return st;
+    if (A->n == 0) return CSRC_OK;
+    if (!x || !y || !yt) return CSRC_ERR_ARG;
+    const int ys = (A->vdtype == CSRC_F64 || plan->o.ydtype == CSRC_F64) ? 8 : 4;
+    const int64_t xspan = (int64_t)A->n * xbytes(A->vdtype), yspan = (int64_t)A->n * ys;
+    if (overlap(x, xspan, y, yspan) || overlap(x, xspan, yt, yspan) || overlap(y, yspan, yt, yspan))
+        return CSRC_ERR_ALIAS;
+    const bool fused = plan->o.variant == CSRC_V_PRIVATE && plan->o.atomic_merge && !plan->o.persistent &&
+                       lds_private_pair(plan->max_span, plan->max_tile_entries, plan->max_intervals,
+                                        acc_bytes(A->vdtype)) <= kLdsBudget;
+    if (!fused) {
+        st = product(A, plan, 1, x, 1, y, 1, workspace, ws_bytes, stream, false);
+        return st ? st : product(A, plan, 1, x, 1, yt, 1, workspace, ws_bytes, stream, true);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (A->vdtype) {
+    case CSRC_F64: return launch_pair<F64T, double>(plan, A, x, y, yt, workspace, s);
+    case CSRC_F32:
+        return plan->o.ydtype == CSRC_F64 ? launch_pair<F32T, double>(plan, A, x, y, yt, workspace, s)
+                                          : launch_pair<F32T, float>(plan, A, x, y, yt, workspace, s);
+    case CSRC_BF16:
+        return plan->o.ydtype == CSRC_F64 ? launch_pair<B16T, double>(plan, A, x, y, yt, workspace, s)
+                                          : launch_pair<B16T, float>(plan, A, x, y, yt, workspace, s);
+    default: return CSRC_ERR_ARG;
+    }
 }
 
 // ------------------------------------------------------------ batch launches

@@ -41,6 +41,11 @@ inline int64_t lds_private(int64_t smax, int64_t emax, int64_t ivmax, int acc)
 {
     return lds_xs(smax, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
+// PRIVATE producing A x and A^T x together: the sums of both products
+inline int64_t lds_private_pair(int64_t smax, int64_t emax, int64_t ivmax, int acc)
+{
+    return lds_xs(smax, acc) + align16(smax * kSumBytes) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+}
 // one buffer of the persistent PRIVATE kernel: x and sums of own rows and
 // window intervals, each padded to 16-byte chunks of x (spad values), row ids
 inline int64_t lds_private_padded(int64_t spad, int64_t emax, int acc)
