@@ -178,6 +178,59 @@ def spmm(c, X, **override):
     return Y
 
 
+def split_rect(n, m, rowptr, col, val):
+    """Sec. 2.1: an n x m matrix (m >= n) as A_S + A_R.  A_S (n x n) holds
+    the entries of columns < n and goes to CSRC; A_R holds those of columns
+    >= n as CSR (``iar`` int32[n+1], ``jar`` int32 global column indices,
+    ``ar`` float64), each row in input order.  Returns (CSR of A_S as
+    (rowptr, col, val), dict(n, m, kr, iar, jar, ar))."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    if m < n or rowptr.shape != (n + 1,) or np.any(col < 0) or np.any(col >= m):
+        raise CsrcError("bad rectangular matrix")
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    sq = col < n
+    s_rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows[sq], minlength=n), out=s_rowptr[1:])
+    iar = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows[~sq], minlength=n), out=iar[1:])
+    r = {"n": n, "m": m, "kr": int(iar[-1]), "iar": iar.astype(np.int32),
+         "jar": col[~sq].astype(np.int32), "ar": val[~sq].copy()}
+    return (s_rowptr, col[sq].astype(np.int32), val[sq].copy()), r
+
+
+def spmv_rect(c, r, x, **override):
+    """y = A x for A = A_S + A_R (Fig. 2b): the square CSRC loop on x[:n],
+    then each row's auxiliary CSR entries gathered from the whole x."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = c["n"]
+    y = spmv(c, x[:n], **override)
+    ar = override.get("ar", r["ar"])
+    iar, jar = r["iar"], r["jar"]
+    for i in range(n):
+        t = y[i]
+        for q in range(iar[i], iar[i + 1]):
+            t += ar[q] * x[jar[q]]
+        y[i] = t
+    return y
+
+
+def spmv_rect_t(c, r, x, **override):
+    """y = A^T x (y has m entries): A_S^T x on the first n, and each entry
+    of A_R scattered into y[jar] (the transpose of the auxiliary CSR)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n, m = c["n"], r["m"]
+    y = np.zeros(m, dtype=np.float64)
+    y[:n] = spmv_t(c, x, **override)
+    ar = override.get("ar", r["ar"])
+    iar, jar = r["iar"], r["jar"]
+    for i in range(n):
+        for q in range(iar[i], iar[i + 1]):
+            y[jar[q]] += ar[q] * x[i]
+    return y
+
+
 def spmv_py(c, x, transpose=False):
     """Pure-Python Fig. 2a loop (tiny inputs): same order as the C oracle."""
     n = c["n"]

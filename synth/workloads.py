@@ -42,6 +42,40 @@ def hex_mesh(side=100, ordering="natural", kind="uniform"):
     return a, x
 
 
+def rect_mesh(side=17, extra=None, kind="uniform"):
+    """An n x m matrix of the overlapping-subdomain kind (Sec. 2.1): the
+    27-point mesh of side^3 nodes (its own rows and columns) plus couplings
+    of the nodes of the top face (z = side - 1) to `extra` overlap nodes
+    numbered n .. m-1 (each top node couples to the overlap nodes above it
+    and its grid neighbours').  Returns (CSR n x m, x of m values)."""
+    a = P.q1_hex(side, side, side)
+    fill_values(a, 1005, kind)
+    n = a.n
+    ex = extra if extra is not None else side * side
+    rows, cols = [], []
+    top = np.arange(n - side * side, n)
+    for d in (-1, 0, 1):
+        tgt = (top - (n - side * side)) + d
+        ok = (tgt >= 0) & (tgt < ex)
+        rows.append(top[ok])
+        cols.append(n + tgt[ok])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    u = uniform01(1006, 5, rows.astype(np.int64) * (n + ex) + cols)
+    vals = np.round(16 * u - 8) if kind == "int" else 2.0 * u - 1.0
+    base_rows = np.repeat(np.arange(n), np.diff(a.rowptr))
+    all_rows = np.concatenate([base_rows, rows])
+    all_cols = np.concatenate([a.col.astype(np.int64), cols])
+    all_vals = np.concatenate([a.val, vals])
+    order = np.lexsort((all_cols, all_rows))
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(all_rows, minlength=n), out=rowptr[1:])
+    m = n + ex
+    ux = uniform01(1105, 6, np.arange(m, dtype=np.int64))
+    x = np.round(16 * ux - 8) if kind == "int" else 2.0 * ux - 1.0
+    return (n, m, rowptr, all_cols[order].astype(np.int32), all_vals[order]), x
+
+
 def tet_mesh(side=80, dof=3, kind="uniform"):
     a = P.kuhn_tet(side, side, side, dof)
     fill_values(a, 1003, kind)

@@ -206,3 +206,21 @@ def test_numerically_symmetric_storage(name):
     y = R.spmv(c, x)
     assert np.array_equal(y, R.spmv_t(c, x))
     assert rel_inf(y, A @ x) <= 1e-14
+
+
+@pytest.mark.parametrize("side", [5, 9])
+def test_rectangular_product(side):
+    """Sec. 2.1 / Fig. 2b: A (n x m) = A_S + A_R.  The split rebuilds A
+    exactly, and the oracle's A x and A^T x equal scipy's products with the
+    whole rectangular matrix."""
+    (n, m, rowptr, col, val), x = W.rect_mesh(side)
+    A = sp.csr_matrix((val, col, rowptr), shape=(n, m))
+    (srp, scol, sval), r = R.split_rect(n, m, rowptr, col, val)
+    assert r["kr"] > 0 and np.all(r["jar"] >= n) and np.all(scol < n)
+    S = sp.csr_matrix((sval, scol, srp), shape=(n, m))
+    Rm = sp.csr_matrix((r["ar"], r["jar"], r["iar"]), shape=(n, m))
+    assert abs(S + Rm - A).max() == 0.0
+    c = R.csr_to_csrc(n, srp, scol, sval)
+    assert rel_inf(R.spmv_rect(c, r, x), A @ x) <= 1e-14
+    xt = x[:n]
+    assert rel_inf(R.spmv_rect_t(c, r, xt), A.T @ xt) <= 1e-14
