@@ -103,6 +103,26 @@ int csrc_from_csr(int32_t n, const int64_t *row_ptr, const int32_t *col,
                   int32_t *ia, int32_t *ja, double *ad, double *al, double *au);
 
 /*
+ * Rectangular matrices (Sec. 2.1): an n x m matrix A with m >= n is
+ * A_S + A_R, where A_S (n x n, the entries of columns < n) has a symmetric
+ * pattern and goes to CSRC (csrc_count / csrc_from_csr on the square CSR
+ * that csrc_rect_split writes) and A_R (the entries of columns >= n) stays
+ * in CSR with global column indices.
+ *
+ * csrc_rect_count -- validate the n x m CSR (row_ptr[n+1], col) and count
+ *   the entries of A_S (nnz_s) and of A_R (nnz_r).  Errors: ARG, INDEX_RANGE
+ *   (a column outside [0, m)), TOO_LARGE (nnz_r >= 2^31).
+ * csrc_rect_split -- write A_S as CSR (s_row_ptr[n+1], s_col[nnz_s],
+ *   s_val[nnz_s]) and A_R as iar[n+1], jar[nnz_r], ar[nnz_r]; each row keeps
+ *   its input order.  Host memory owned by the caller; same errors.
+ */
+int csrc_rect_count(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col,
+                    int64_t *nnz_s, int64_t *nnz_r);
+int csrc_rect_split(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col,
+                    const double *val, int64_t *s_row_ptr, int32_t *s_col, double *s_val,
+                    int32_t *iar, int32_t *jar, double *ar);
+
+/*
  * csrc_quantize -- round FP64 values to a storage type, host to host.
  *   dtype CSRC_F32: IEEE round-to-nearest-even; CSRC_BF16: RNE of the FP32
  *   value to bfloat16 (dst holds uint16 bit patterns); CSRC_F64: copy.
@@ -287,6 +307,33 @@ int csrc_spmv_t(const csrc_matrix *A, const csrc_plan *plan, const void *x,
  */
 int csrc_spmv_pair(const csrc_matrix *A, const csrc_plan *plan, const void *x,
                    void *y, void *yt, void *workspace, int64_t ws_bytes, void *stream);
+
+/* The auxiliary CSR part A_R of a rectangular matrix, on the device: m
+ * columns in total, kr entries, values of the matrix's vdtype. */
+typedef struct csrc_rect {
+    int32_t m;
+    int32_t vdtype;
+    int64_t kr;
+    const int32_t *iar;    /* device, n+1 */
+    const int32_t *jar;    /* device, kr; columns in [n, m) */
+    const void *ar;        /* device, kr  */
+} csrc_rect;
+
+/*
+ * csrc_spmv_rect -- y <- A x for A = A_S + A_R (Fig. 2b): x has m entries,
+ *   y has n.  The square product of A (any plan) on x[0, n), then each row
+ *   gathers its A_R entries from x.
+ * csrc_spmv_rect_t -- y <- A^T x: x has n entries, y has m; y[0, n) is the
+ *   square transpose product and y[n, m) receives A_R's entries scattered
+ *   with atomics (the paper stops at A x; this is the transpose of the same
+ *   matrix).
+ * R->vdtype must equal A->vdtype; x and y must not overlap (CSRC_ERR_ALIAS).
+ * Other arguments and errors as for csrc_spmv.
+ */
+int csrc_spmv_rect(const csrc_matrix *A, const csrc_rect *R, const csrc_plan *plan,
+                   const void *x, void *y, void *workspace, int64_t ws_bytes, void *stream);
+int csrc_spmv_rect_t(const csrc_matrix *A, const csrc_rect *R, const csrc_plan *plan,
+                     const void *x, void *y, void *workspace, int64_t ws_bytes, void *stream);
 
 /*
  * csrc_spmm / csrc_spmm_t -- Y <- A X (or A^T X) for r right-hand sides.

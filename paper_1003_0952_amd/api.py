@@ -56,6 +56,28 @@ def csrc_from_csr(n, rowptr, col, val, pad=False):
     return {"n": n, "k": k, "ia": ia, "ja": ja, "ad": ad, "al": al, "au": au}
 
 
+def csrc_rect_split(n, m, rowptr, col, val):
+    """An n x m CSR matrix (m >= n) as A_S + A_R (Sec. 2.1), on the host
+    (library code): returns (CSR of A_S as (rowptr, col, val), dict of A_R
+    with n, m, kr, iar, jar, ar)."""
+    n, m = int(n), int(m)
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    ns, nr = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(B.lib.csrc_rect_count(n, m, np_ptr(rowptr), np_ptr(col), ctypes.byref(ns), ctypes.byref(nr)),
+          "csrc_rect_count")
+    srp = np.zeros(n + 1, np.int64)
+    scol = np.zeros(ns.value, np.int32)
+    sval = np.zeros(ns.value, np.float64)
+    iar = np.zeros(n + 1, np.int32)
+    jar = np.zeros(nr.value, np.int32)
+    ar = np.zeros(nr.value, np.float64)
+    check(B.lib.csrc_rect_split(n, m, np_ptr(rowptr), np_ptr(col), np_ptr(val), np_ptr(srp), np_ptr(scol),
+                                np_ptr(sval), np_ptr(iar), np_ptr(jar), np_ptr(ar)), "csrc_rect_split")
+    return (srp, scol, sval), {"n": n, "m": m, "kr": int(nr.value), "iar": iar, "jar": jar, "ar": ar}
+
+
 def csrc_quantize(a, dtype):
     d = _dt(dtype)
     a = np.ascontiguousarray(a, dtype=np.float64)
@@ -129,6 +151,22 @@ class Matrix:
         vb = {B.F64: 8, B.F32_: 4, B.BF16: 2}[self.vdtype]
         nv = 1 if self.symmetric else 2
         return 4 * (self.n + 1) + self.k * (4 + nv * vb) + self.n * vb
+
+
+class RectPart:
+    """The auxiliary CSR part A_R of a rectangular matrix in device memory,
+    stored as ``dtype`` like its square part."""
+
+    def __init__(self, r, dtype="f64", device="cuda"):
+        import torch
+        self.n, self.m, self.kr = int(r["n"]), int(r["m"]), int(r["kr"])
+        self.vdtype = _dt(dtype)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        self.iar = t(np.asarray(r["iar"], dtype=np.int32))
+        self.jar = t(np.asarray(r["jar"], dtype=np.int32))
+        self.ar = t(csrc_quantize(r["ar"], self.vdtype))
+        self.desc = B.CsrcRect(self.m, self.vdtype, self.kr, t_ptr(self.iar).value or 0,
+                               t_ptr(self.jar).value or 0, t_ptr(self.ar).value or 0)
 
 
 class Plan:
@@ -212,6 +250,20 @@ def csrc_spmv_pair(A, plan, x, y, yt, stream=None):
     check(B.lib.csrc_spmv_pair(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y), t_ptr(yt),
                                t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_pair")
     return y, yt
+
+
+def csrc_spmv_rect(A, R, plan, x, y, stream=None):
+    """y (n) <- (A_S + A_R) x (m), Fig. 2b.  Asynchronous on the stream."""
+    check(B.lib.csrc_spmv_rect(ctypes.byref(A.desc), ctypes.byref(R.desc), plan.handle, t_ptr(x), t_ptr(y),
+                               t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_rect")
+    return y
+
+
+def csrc_spmv_rect_t(A, R, plan, x, y, stream=None):
+    """y (m) <- (A_S + A_R)^T x (n).  Asynchronous on the stream."""
+    check(B.lib.csrc_spmv_rect_t(ctypes.byref(A.desc), ctypes.byref(R.desc), plan.handle, t_ptr(x), t_ptr(y),
+                                 t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_rect_t")
+    return y
 
 
 def csrc_spmm(A, plan, X, Y, stream=None):

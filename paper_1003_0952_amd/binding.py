@@ -79,6 +79,10 @@ class CsrcMatrix(ctypes.Structure):
                 ("ad", P), ("al", P), ("au", P)]
 
 
+class CsrcRect(ctypes.Structure):
+    _fields_ = [("m", I32), ("vdtype", I32), ("kr", I64), ("iar", P), ("jar", P), ("ar", P)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("variant", I32), ("tile_work", I32), ("lanes", I32), ("block", I32),
                 ("color_criterion", I32), ("ydtype", I32), ("compensated", I32),
@@ -110,6 +114,10 @@ _sig("csrc_last_hip_error", I32, [])
 _sig("csrc_last_hip_error_string", ctypes.c_char_p, [])
 _sig("csrc_count", ctypes.c_int, [I32, P, P, I32, P])
 _sig("csrc_from_csr", ctypes.c_int, [I32, P, P, P, I32, P, P, P, P, P])
+_sig("csrc_rect_count", ctypes.c_int, [I32, I32, P, P, P, P])
+_sig("csrc_rect_split", ctypes.c_int, [I32, I32, P, P, P, P, P, P, P, P, P])
+_sig("csrc_spmv_rect", ctypes.c_int, [P, P, P, P, P, P, I64, P])
+_sig("csrc_spmv_rect_t", ctypes.c_int, [P, P, P, P, P, P, I64, P])
 _sig("csrc_quantize", ctypes.c_int, [I64, P, I32, P])
 _sig("csrc_plan_opts_default", ctypes.c_int, [I32, P])
 _sig("csrc_plan_create", ctypes.c_int, [I32, P, P, I32, P, P])

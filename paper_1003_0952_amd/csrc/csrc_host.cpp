@@ -178,6 +178,66 @@ extern "C" int csrc_count(int32_t n, const int64_t *row_ptr, const int32_t *col,
     }
 }
 
+// Rectangular matrices (Sec. 2.1): the entries of columns < n form A_S, the
+// others A_R; both keep each row's input order.
+static int rect_check(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col)
+{
+    if (n < 0 || m < n || (n > 0 && !row_ptr)) return CSRC_ERR_ARG;
+    if (n == 0) return CSRC_OK;
+    if (row_ptr[0] != 0) return CSRC_ERR_ARG;
+    for (int32_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return CSRC_ERR_ARG;
+    if (row_ptr[n] > 0 && !col) return CSRC_ERR_ARG;
+    for (int64_t q = 0; q < row_ptr[n]; ++q)
+        if (col[q] < 0 || col[q] >= m) return CSRC_ERR_INDEX_RANGE;
+    return CSRC_OK;
+}
+
+extern "C" int csrc_rect_count(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col, int64_t *nnz_s,
+                               int64_t *nnz_r)
+{
+    if (!nnz_s || !nnz_r) return CSRC_ERR_ARG;
+    int st = rect_check(n, m, row_ptr, col);
+    if (st) return st;
+    int64_t s = 0, r = 0;
+    for (int64_t q = 0; n > 0 && q < row_ptr[n]; ++q) (col[q] < n ? s : r) += 1;
+    if (r >= (int64_t(1) << 31)) return CSRC_ERR_TOO_LARGE;
+    *nnz_s = s;
+    *nnz_r = r;
+    return CSRC_OK;
+}
+
+extern "C" int csrc_rect_split(int32_t n, int32_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
+                               int64_t *s_row_ptr, int32_t *s_col, double *s_val, int32_t *iar, int32_t *jar,
+                               double *ar)
+{
+    if (!s_row_ptr || !iar) return CSRC_ERR_ARG;
+    int st = rect_check(n, m, row_ptr, col);
+    if (st) return st;
+    s_row_ptr[0] = 0;
+    iar[0] = 0;
+    if (n == 0) return CSRC_OK;
+    if (row_ptr[n] > 0 && !val) return CSRC_ERR_ARG;
+    int64_t s = 0, r = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+            if (col[q] < n) {
+                if (!s_col || !s_val) return CSRC_ERR_ARG;
+                s_col[s] = col[q];
+                s_val[s++] = val[q];
+            } else {
+                if (!jar || !ar) return CSRC_ERR_ARG;
+                if (r >= (int64_t(1) << 31) - 1) return CSRC_ERR_TOO_LARGE;
+                jar[r] = col[q];
+                ar[r++] = val[q];
+            }
+        }
+        s_row_ptr[i + 1] = s;
+        iar[i + 1] = (int32_t)r;
+    }
+    return CSRC_OK;
+}
+
 extern "C" int csrc_from_csr(int32_t n, const int64_t *row_ptr, const int32_t *col,
                              const double *val, int32_t flags, int32_t *ia, int32_t *ja,
                              double *ad, double *al, double *au)

@@ -283,15 +283,6 @@ struct NoHook {
 // inside the stream loop.
 __device__ __forceinline__ void settle_loads() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Stream entries [kb, k1) of the block (kb = k0 rounded down to even).  `cur`
-// holds the first batch, issued by the caller before its staging.  For each
-// entry of row r (relative) with column j: x_j = ent(j, au * s_x[r]) scatters
-// and gathers, and a lane's run of gathered products of one row goes to
-// flush(r, sum).  With LOAD_AU false, an au pair is fetched only if need_au(j)
-// holds for one of its entries (else its products are zero and ent ignores
-// them).  The batch loop runs the same number of times in every lane (lanes
-// past k1 see only kNoRow), so after_first() is called once, by all lanes
-// together, after the first batch.
 // Lane exchange inside groups of 4 and 8 lanes (DPP: quad permutation and
 // half-row mirror), for 32- and 64-bit values.  Every lane of the wave must
 // be active.
@@ -2057,6 +2048,107 @@ extern "C" int csrc_spmv_pair(const csrc_matrix *A, const csrc_plan *plan, const
                                           : launch_pair<B16T, float>(plan, A, x, y, yt, workspace, s);
     default: return CSRC_ERR_ARG;
     }
+}
+
+// ------------------------------------------------------------ rectangular
+
+namespace csrc {
+
+// Rows of A_R (Sec. 2.1, Fig. 2b): y_i += the row's auxiliary CSR entries
+// ar x[jar] (rows of A_R are short: one thread per row, no race).
+template <class VT, class YT>
+__global__ __launch_bounds__(256) void k_rect_gather(int32_t n, const int32_t *__restrict__ iar,
+                                                     const int32_t *__restrict__ jar,
+                                                     const typename VT::V *__restrict__ ar,
+                                                     const typename VT::X *__restrict__ x, YT *__restrict__ y)
+{
+    using A = typename VT::A;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int q0 = iar[i], q1 = iar[i + 1];
+        if (q0 == q1) continue;
+        A t = A(0);
+        for (int q = q0; q < q1; ++q) t += (A)ldv(ar, q) * (A)x[jar[q]];
+        y[i] = y[i] + (YT)t;
+    }
+}
+
+// Transpose of A_R: every entry (i, jar) adds ar x_i to y[jar] (global
+// atomics; y[n, m) is cleared first).
+template <class VT, class YT>
+__global__ __launch_bounds__(256) void k_rect_scatter(int32_t n, const int32_t *__restrict__ iar,
+                                                      const int32_t *__restrict__ jar,
+                                                      const typename VT::V *__restrict__ ar,
+                                                      const typename VT::X *__restrict__ x, YT *__restrict__ y)
+{
+    using A = typename VT::A;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int q0 = iar[i], q1 = iar[i + 1];
+        if (q0 == q1) continue;
+        const A xi = (A)x[i];
+        for (int q = q0; q < q1; ++q) atomic_add(&y[jar[q]], (YT)((A)ldv(ar, q) * xi));
+    }
+}
+
+template <class VT, class YT>
+static int launch_rect(const csrc_rect *R, int32_t n, const void *x, void *y, bool transpose, hipStream_t s)
+{
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ((int64_t)n + 255) / 256));
+    const auto *ar = static_cast<const typename VT::V *>(R->ar);
+    const auto *xv = static_cast<const typename VT::X *>(x);
+    YT *yv = static_cast<YT *>(y);
+    if (transpose) {
+        if (R->m > n) k_fill_zero<YT><<<fill_grid(R->m - n), 256, 0, s>>>(yv + n, R->m - n, 1, 1);
+        if (R->kr > 0) k_rect_scatter<VT, YT><<<grid, 256, 0, s>>>(n, R->iar, R->jar, ar, xv, yv);
+    } else if (R->kr > 0) {
+        k_rect_gather<VT, YT><<<grid, 256, 0, s>>>(n, R->iar, R->jar, ar, xv, yv);
+    }
+    return hip_status(hipGetLastError());
+}
+
+static int rect_product(const csrc_matrix *A, const csrc_rect *R, const csrc_plan *p, const void *x, void *y,
+                        void *ws, int64_t ws_bytes, void *stream, bool transpose)
+{
+    if (!R) return CSRC_ERR_ARG;
+    int st = check_call(A, p, ws, ws_bytes);
+    if (st) return st;
+    if (R->vdtype != A->vdtype || R->m < A->n || R->kr < 0 || (A->n > 0 && !R->iar) ||
+        (R->kr > 0 && (!R->jar || !R->ar)))
+        return CSRC_ERR_ARG;
+    const int32_t n = A->n;
+    if (R->m == 0) return CSRC_OK;
+    if (!x || !y) return CSRC_ERR_ARG;
+    const int ys = (A->vdtype == CSRC_F64 || p->o.ydtype == CSRC_F64) ? 8 : 4;
+    const int64_t xn = transpose ? n : R->m, yn = transpose ? R->m : n;
+    if (overlap(x, xn * xbytes(A->vdtype), y, yn * ys)) return CSRC_ERR_ALIAS;
+    if (n > 0) {
+        st = product(A, p, 1, x, 1, y, 1, ws, ws_bytes, stream, transpose);
+        if (st) return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (A->vdtype) {
+    case CSRC_F64: return launch_rect<F64T, double>(R, n, x, y, transpose, s);
+    case CSRC_F32:
+        return p->o.ydtype == CSRC_F64 ? launch_rect<F32T, double>(R, n, x, y, transpose, s)
+                                       : launch_rect<F32T, float>(R, n, x, y, transpose, s);
+    case CSRC_BF16:
+        return p->o.ydtype == CSRC_F64 ? launch_rect<B16T, double>(R, n, x, y, transpose, s)
+                                       : launch_rect<B16T, float>(R, n, x, y, transpose, s);
+    default: return CSRC_ERR_ARG;
+    }
+}
+
+}  // namespace csrc
+
+extern "C" int csrc_spmv_rect(const csrc_matrix *A, const csrc_rect *R, const csrc_plan *plan, const void *x,
+                              void *y, void *workspace, int64_t ws_bytes, void *stream)
+{
+    return csrc::rect_product(A, R, plan, x, y, workspace, ws_bytes, stream, false);
+}
+
+extern "C" int csrc_spmv_rect_t(const csrc_matrix *A, const csrc_rect *R, const csrc_plan *plan, const void *x,
+                                void *y, void *workspace, int64_t ws_bytes, void *stream)
+{
+    return csrc::rect_product(A, R, plan, x, y, workspace, ws_bytes, stream, true);
 }
 
 // ------------------------------------------------------------ batch launches

@@ -290,3 +290,25 @@ def test_features_match_oracle(make):
     c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
     got = C.csrc_features(c["ia"], c["ja"], "f64", -1)
     assert np.allclose(got, OF.features(c), rtol=2e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("side", [3, 6])
+def test_rect_split_bit_exact(side):
+    """The library's A_S / A_R split (Sec. 2.1) equals the oracle's."""
+    (n, m, rowptr, col, val), _ = W.rect_mesh(side)
+    (srp, scol, sval), r = C.csrc_rect_split(n, m, rowptr, col, val)
+    (orp, ocol, oval), o = R.split_rect(n, m, rowptr, col, val)
+    assert np.array_equal(srp, orp) and np.array_equal(scol, ocol) and np.array_equal(sval, oval)
+    for key in ("iar", "jar", "ar"):
+        assert np.array_equal(r[key], o[key]), key
+    assert r["kr"] == o["kr"] and r["m"] == m
+
+
+def test_rect_split_rejects_bad_columns():
+    rowptr = np.array([0, 2, 3], np.int64)
+    col = np.array([0, 5, 1], np.int32)
+    with pytest.raises(C.CsrcError) as e:
+        C.csrc_rect_split(2, 4, rowptr, col, np.ones(3))
+    assert e.value.status == B.ERR_INDEX_RANGE
+    with pytest.raises(C.CsrcError):
+        C.csrc_rect_split(3, 2, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0))   # m < n
