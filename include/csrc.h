@@ -179,7 +179,20 @@ typedef enum csrc_variant {
        rows above it that scatter into the tile, so every y entry is formed
        by one workgroup in LDS and stored once; no partials, no atomics.      */
     CSRC_V_OWNER = 4,
-    CSRC_V_COUNT = 5
+    /* Colour classes with a bounded stride (the refinement of the colourful
+       method proposed in Sec. 5): the classes are built from tiles of
+       consecutive rows (at most 2048) instead of single rows.  Each tile
+       works in LDS as PRIVATE does; two tiles conflict iff the rows they
+       write (their own rows and their window intervals) meet, and a greedy
+       first-fit colouring in ascending tile order splits the tiles into
+       conflict-free classes.  y is cleared, then one launch per class adds
+       every tile's sums to y with plain read-modify-writes: no global
+       atomics and no partial buffer.  The tiles' sums reach y in a fixed
+       class order; inside a tile the LDS additions, as in every tile
+       variant, come in the order the waves run.  One right-hand side
+       (max_rhs 1).                                                           */
+    CSRC_V_TILE_COLOR = 5,
+    CSRC_V_COUNT = 6
 } csrc_variant;
 
 /* Colouring criteria (Sec. 3.2). */
@@ -248,7 +261,7 @@ int csrc_plan_upload(const csrc_plan *plan, void *workspace, int64_t bytes,
 typedef struct csrc_plan_info {
     int32_t variant;
     int32_t ntiles;         /* workgroup tiles (0 for PLAIN)                   */
-    int32_t ncolors;        /* colour classes (COLOR)                          */
+    int32_t ncolors;        /* colour classes (COLOR, TILE_COLOR)              */
     int32_t lanes;
     int32_t block;
     int32_t max_tile_rows;
@@ -265,7 +278,8 @@ int csrc_plan_get_info(const csrc_plan *plan, csrc_plan_info *info);
 /*
  * csrc_plan_export -- copy host-side plan tables (for verification):
  *   what 0: tile boundaries, ntiles+1 int32
- *   what 1: row colours, n int32 (COLOR)
+ *   what 1: row colours, n int32 (COLOR); tile colours, ntiles int32
+ *           (TILE_COLOR)
  *   what 2: window intervals, 3*nintervals int32 triples
  *           (tile, first row, row count), ascending by tile then row
  * count is the capacity of dst in int32 elements; the needed count is

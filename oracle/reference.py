@@ -357,6 +357,23 @@ def out_of_tile_targets(c, r0, r1):
     return t[t < r0]
 
 
+def color_blocks(write_sets):
+    """Colour classes of row blocks with a bounded stride (the refinement of
+    the colourful method proposed in Sec. 5): block b writes the rows in
+    ``write_sets[b]``; blocks b and d conflict iff those sets meet.  Greedy
+    first-fit in ascending block order, as in Sec. 3.2 for rows.  Returns
+    (colour per block, number of colours)."""
+    sets = [set(int(r) for r in w) for w in write_sets]
+    col = []
+    for b, wb in enumerate(sets):
+        used = {col[d] for d in range(b) if wb & sets[d]}
+        k = 0
+        while k in used:
+            k += 1
+        col.append(k)
+    return np.array(col, dtype=np.int32), (max(col) + 1 if col else 0)
+
+
 # --------------------------------------------------------------------------
 # Reduced precision: rounding and error bounds
 # --------------------------------------------------------------------------

@@ -49,8 +49,9 @@ ERR_NOMEM = -11
 F64, F32_, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32_, "bf16": BF16}
 
-PLAIN, ATOMIC, PRIVATE, COLOR, OWNER = 0, 1, 2, 3, 4
-VARIANTS = {"plain": PLAIN, "atomic": ATOMIC, "private": PRIVATE, "color": COLOR, "owner": OWNER}
+PLAIN, ATOMIC, PRIVATE, COLOR, OWNER, TILE_COLOR = 0, 1, 2, 3, 4, 5
+VARIANTS = {"plain": PLAIN, "atomic": ATOMIC, "private": PRIVATE, "color": COLOR, "owner": OWNER,
+            "tile_color": TILE_COLOR}
 VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 
 PAD_PATTERN = 1

@@ -108,6 +108,9 @@ static int default_tile_work(int32_t variant)
     case CSRC_V_ATOMIC: return 8192;
     case CSRC_V_PRIVATE: return 8192;
     case CSRC_V_OWNER: return 16384;
+    // a class holds about n / bandwidth tiles whatever their size: large
+    // tiles keep the number of classes (launches) small
+    case CSRC_V_TILE_COLOR: return 32768;
     default: return 4096;
     }
 }
@@ -126,6 +129,7 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
     if (o.persistent && (o.variant != CSRC_V_PRIVATE || (o.block != 0 && o.block != 512))) return CSRC_ERR_ARG;
     if (o.atomic_merge < 0 || o.atomic_merge > 1) return CSRC_ERR_ARG;
     if (o.atomic_merge && (o.variant != CSRC_V_PRIVATE || o.persistent || o.compensated)) return CSRC_ERR_ARG;
+    if (o.variant == CSRC_V_TILE_COLOR && o.max_rhs > 1) return CSRC_ERR_ARG;
     if (vdtype != CSRC_F64 && o.ydtype != CSRC_F32 && o.ydtype != CSRC_F64) return CSRC_ERR_ARG;
     *out = nullptr;
     csrc_plan *p = nullptr;
@@ -171,7 +175,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             }
         }
 
-        if (v == CSRC_V_PRIVATE && n > 0) {
+        const bool windows = v == CSRC_V_PRIVATE || v == CSRC_V_TILE_COLOR;
+        if (windows && n > 0) {
             // Effective range of a tile (Sec. 3.1): its own rows plus the
             // rows below it that its loops write.  The latter are stored as a
             // few intervals (windows) whose slots hold the tile's partials.
@@ -275,6 +280,49 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 
+        if (v == CSRC_V_TILE_COLOR && n > 0) {
+            // Colour classes of tiles (the bounded-stride classes proposed in
+            // Sec. 5).  The rows tile t writes are its own rows and every row
+            // of its window intervals; rows -> writing tiles as a CSR filled
+            // in ascending tile order, then greedy first-fit over the tiles.
+            std::vector<int64_t> wptr((size_t)n + 1, 0);
+            for (int32_t t = 0; t < p->ntiles; ++t) {
+                for (int32_t r = p->tiles[t]; r < p->tiles[t + 1]; ++r) wptr[r + 1]++;
+                for (int32_t g = p->iv_ptr[t]; g < p->iv_ptr[t + 1]; ++g)
+                    for (int32_t r = p->iv_row[g]; r < p->iv_row[g] + p->iv_len[g]; ++r) wptr[r + 1]++;
+            }
+            for (int32_t i = 0; i < n; ++i) wptr[i + 1] += wptr[i];
+            std::vector<int32_t> wt((size_t)wptr[n]);
+            std::vector<int64_t> wfill(wptr.begin(), wptr.end() - 1);
+            for (int32_t t = 0; t < p->ntiles; ++t) {
+                for (int32_t r = p->tiles[t]; r < p->tiles[t + 1]; ++r) wt[wfill[r]++] = t;
+                for (int32_t g = p->iv_ptr[t]; g < p->iv_ptr[t + 1]; ++g)
+                    for (int32_t r = p->iv_row[g]; r < p->iv_row[g] + p->iv_len[g]; ++r) wt[wfill[r]++] = t;
+            }
+            p->color.assign(p->ntiles, 0);
+            std::vector<int32_t> forbid;   // forbid[c] == t: colour c taken by a conflicting earlier tile
+            p->ncolors = 0;
+            auto visit = [&](int32_t t, int32_t r) {
+                for (int64_t q = wptr[r]; q < wptr[r + 1] && wt[q] < t; ++q) forbid[p->color[wt[q]]] = t;
+            };
+            for (int32_t t = 0; t < p->ntiles; ++t) {
+                if (forbid.size() < (size_t)p->ncolors + 1) forbid.resize((size_t)p->ncolors + 1, -1);
+                for (int32_t r = p->tiles[t]; r < p->tiles[t + 1]; ++r) visit(t, r);
+                for (int32_t g = p->iv_ptr[t]; g < p->iv_ptr[t + 1]; ++g)
+                    for (int32_t r = p->iv_row[g]; r < p->iv_row[g] + p->iv_len[g]; ++r) visit(t, r);
+                int32_t c = 0;
+                while (forbid[c] == t) ++c;
+                p->color[t] = c;
+                p->ncolors = std::max(p->ncolors, c + 1);
+            }
+            p->cptr.assign(p->ncolors + 1, 0);
+            for (int32_t t = 0; t < p->ntiles; ++t) p->cptr[p->color[t] + 1]++;
+            for (int32_t c = 0; c < p->ncolors; ++c) p->cptr[c + 1] += p->cptr[c];
+            p->crow.resize(p->ntiles);
+            std::vector<int32_t> cf(p->cptr.begin(), p->cptr.end() - 1);
+            for (int32_t t = 0; t < p->ntiles; ++t) p->crow[cf[p->color[t]]++] = t;
+        }
+
         if (v == CSRC_V_OWNER && n > 0) {
             // Rows of later tiles that scatter into tile t, as intervals.
             std::vector<int32_t> tile_of(n);
@@ -354,7 +402,9 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         p->blob_bytes = (int64_t)blob.size();
         p->t_partials.offset = p->blob_bytes;
         // the atomic merge of single products needs no partials
-        p->t_partials.bytes = (p->o.atomic_merge && p->o.max_rhs == 1) ? 0 : p->window_slots * acc * p->o.max_rhs;
+        p->t_partials.bytes = ((p->o.atomic_merge && p->o.max_rhs == 1) || v == CSRC_V_TILE_COLOR)
+                                  ? 0
+                                  : p->window_slots * acc * p->o.max_rhs;
         p->ws_bytes = csrc::align256(p->blob_bytes + p->t_partials.bytes);
         if (v == CSRC_V_PLAIN) p->ws_bytes = 0;
         *out = p;

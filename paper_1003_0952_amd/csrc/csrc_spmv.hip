@@ -669,16 +669,24 @@ struct WindowMap {
 // slots).  x of both ranges is staged in LDS first (s_x, s_xw).  Own rows go
 // to y; window slots go to the partial buffer for the merge pass.  All
 // staging loads and the first batch of entries are in flight together.
-// AM (atomic merge): y is zero beforehand and both the own rows and the
-// window slots are added to y with global atomics; no partials, no pass.
+// Ways a tile's sums reach y (MODE):
+//   kMergePass   own rows stored, window slots to the partial buffer;
+//   kMergeAtomic y is zero beforehand and both the own rows and the window
+//                slots are added to y with global atomics; no partials;
+//   kMergeColor  y is zero beforehand; the launch runs one colour class of
+//                tiles (tlist), whose written rows are disjoint, so both are
+//                added to y with plain read-modify-writes.
 // Pairs per lane in one batch of the PRIVATE stream.  Three or four pairs
 // put more bytes in flight per wave but cost registers (89 and 115 VGPRs for
 // FP64 against 63) and measured slower on the 27-point and tetrahedral
 // meshes, so two.
 constexpr int kPrivatePairs = 2;
 
-template <class VT, class YT, bool AM>
-__global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
+constexpr int kMergePass = 0, kMergeAtomic = 1, kMergeColor = 2;
+
+template <class VT, class YT, int MODE>
+__global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__restrict__ tlist,
+                                                 const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
                                                  const typename VT::V *__restrict__ ad,
                                                  const typename VT::V *__restrict__ al,
@@ -698,7 +706,8 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
                                                    align16(((int64_t)emax + 4) * 2));
 
     const int tid = threadIdx.x, B = blockDim.x;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = MODE == kMergeColor ? tlist[b] : b;
     NextTile<VT, 2> nt;
     nt.issue(P, t, ia, ad, x);
     A *s_xw = s_x + nt.T;
@@ -723,12 +732,21 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, int64_t kend, const 
     own_stream<VT, true, true>(first, E, s_rid, s_x, [](int) { return true; }, ent, flush);
     __syncthreads();
 
-    if (AM) {
+    if (MODE == kMergeAtomic) {
         for (int i = tid; i < T; i += B) atomic_add(&y[r0 + i], (YT)s_y[i]);
         for (int base = 0; base < W; base += B) {
             const int sl = base + tid;
             const int row = nt.window_row(sl);   // every lane takes part
             if (sl < W) atomic_add(&y[row], (YT)s_w[sl]);
+        }
+        return;
+    }
+    if (MODE == kMergeColor) {
+        for (int i = tid; i < T; i += B) y[r0 + i] += (YT)s_y[i];
+        for (int base = 0; base < W; base += B) {
+            const int sl = base + tid;
+            const int row = nt.window_row(sl);   // every lane takes part
+            if (sl < W) y[row] += (YT)s_w[sl];
         }
         return;
     }
@@ -1832,14 +1850,14 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
             } else if (p->o.atomic_merge) {
                 k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
                 // numerically symmetric storage (au is al): one value load per entry
-                auto kern = al == au ? k_private<SymT<VT>, YT, true> : k_private<VT, YT, true>;
+                auto kern = al == au ? k_private<SymT<VT>, YT, kMergeAtomic> : k_private<VT, YT, kMergeAtomic>;
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
-                kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
+                kern<<<p->ntiles, B, lds, s>>>(P, nullptr, A->ia, A->ja, ad, al, au, x, y, smax, emax);
                 return hip_status(hipGetLastError());
             } else {
-                auto kern = al == au ? k_private<SymT<VT>, YT, false> : k_private<VT, YT, false>;
+                auto kern = al == au ? k_private<SymT<VT>, YT, kMergePass> : k_private<VT, YT, kMergePass>;
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
-                kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, smax, emax);
+                kern<<<p->ntiles, B, lds, s>>>(P, nullptr, A->ia, A->ja, ad, al, au, x, y, smax, emax);
             }
             if (p->nmerge_blocks > 0 && p->window_slots > 0) {
                 if (std::is_same<YT, double>::value)
@@ -1880,6 +1898,20 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
             auto kern = k_owner_mm<VT, YT>;
             if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
             kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, ldx, y, ldy, r, tmax, pmax, emax);
+        }
+        break;
+    }
+    case CSRC_V_TILE_COLOR: {
+        if (!single) return CSRC_ERR_UNSUPPORTED;
+        const int emax = p->max_tile_entries, smax = p->max_span;
+        const size_t lds = (size_t)lds_private(smax, emax, p->max_intervals, sizeof(Acc));
+        auto kern = al == au ? k_private<SymT<VT>, YT, kMergeColor> : k_private<VT, YT, kMergeColor>;
+        if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
+        k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
+        // classes in ascending colour order
+        for (int cl = 0; cl < p->ncolors; ++cl) {
+            const int c0 = p->cptr[cl], c1 = p->cptr[cl + 1];
+            kern<<<c1 - c0, B, lds, s>>>(P, P.crow + c0, A->ia, A->ja, ad, al, au, x, y, smax, emax);
         }
         break;
     }

@@ -19,7 +19,7 @@ from tests.helpers import oracle_csrc, rel_inf
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_atomic"]
+VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_atomic", "tile_color"]
 
 
 def run(C, torch, host, x, variant, dtype, ydtype, transpose=False, **kw):

@@ -13,7 +13,7 @@ from tests.test_gpu_spmv import make_plan
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["private_atomic", "private", "plain", "color", "owner"]
+VARIANTS = ["private_atomic", "private", "plain", "color", "owner", "tile_color"]
 
 
 def setup(C, side, kind, dtype="f64"):

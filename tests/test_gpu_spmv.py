@@ -15,7 +15,7 @@ from tests.helpers import small_cases, oracle_csrc, rel_inf
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_persistent", "private_atomic"]
+VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_persistent", "private_atomic", "tile_color"]
 TOL = 1e-12
 
 
@@ -161,3 +161,27 @@ def test_persistent_schedules(torch_cuda, case, tile_work, grid):
         y, _ = run(torch_cuda, C, host, x, "private_persistent", transpose, tile_work=tile_work, grid=grid)
         ref = (R.spmv_t if transpose else R.spmv)(c, x)
         assert rel_inf(y, ref) <= TOL, (name, tile_work, grid, transpose, rel_inf(y, ref))
+
+
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("tile_work", [300, 1500, 6000])
+def test_tile_colour_classes(torch_cuda, case, tile_work):
+    """Bounded-stride colour classes of tiles: parity for small tiles (many
+    tiles and classes); repeated products agree to rounding (the LDS
+    additions inside a tile come in the order the waves run)."""
+    import paper_1003_0952_amd as C
+    torch = torch_cuda
+    name, a, x = CASES[case]
+    print(f"case {name} tile_color tile_work {tile_work}", flush=True)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    for transpose in (False, True):
+        y, plan = run(torch, C, host, x, "tile_color", transpose, tile_work=tile_work)
+        ref = (R.spmv_t if transpose else R.spmv)(c, x)
+        assert rel_inf(y, ref) <= TOL, (name, tile_work, transpose, rel_inf(y, ref))
+        info = plan.info()
+        assert 1 <= info["ncolors"] <= info["ntiles"]
+        if name.startswith("hex17") and tile_work == 300:
+            assert info["ncolors"] > 2, info
+        y2, _ = run(torch, C, host, x, "tile_color", transpose, tile_work=tile_work)
+        assert rel_inf(y, y2) <= 1e-15, (name, tile_work, transpose)

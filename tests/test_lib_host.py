@@ -312,3 +312,33 @@ def test_rect_split_rejects_bad_columns():
     assert e.value.status == B.ERR_INDEX_RANGE
     with pytest.raises(C.CsrcError):
         C.csrc_rect_split(3, 2, np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0))   # m < n
+
+
+@pytest.mark.parametrize("make", MATS[:5])
+@pytest.mark.parametrize("work", [1024, 4096])
+def test_tile_colour_classes(make, work):
+    """TILE_COLOR plan: tiles as PRIVATE's, window intervals covering each
+    tile's effective range (Sec. 3.1), and tile colours equal to the oracle's
+    greedy first-fit over the rows each tile writes (bit-exact)."""
+    c, h = host_matrix(make())
+    p = HostPlan(h, "tile_color", tile_work=work)
+    tiles = p.export(0)
+    assert np.array_equal(tiles, R.partition_for_target(c["ia"], work, 2048))
+    iv = p.export(2).reshape(-1, 3)
+    sets = []
+    for t in range(len(tiles) - 1):
+        r0, r1 = tiles[t], tiles[t + 1]
+        mine = iv[iv[:, 0] == t]
+        win = np.concatenate([np.arange(s, s + L) for _, s, L in mine]) if len(mine) else np.zeros(0, int)
+        assert np.all(np.isin(R.out_of_tile_targets(c, r0, r1), win))
+        sets.append(np.concatenate([np.arange(r0, r1), win]))
+    col = p.export(1)
+    ref, nref = R.color_blocks(sets)
+    assert np.array_equal(col, ref)
+    assert p.info()["ncolors"] == nref
+
+
+def test_tile_colour_options_rejected():
+    c, h = host_matrix(W.quad64()[0])
+    with pytest.raises(C.CsrcError):
+        HostPlan(h, "tile_color", max_rhs=4)

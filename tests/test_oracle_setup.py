@@ -130,3 +130,48 @@ def test_row_cap():
     assert list(capped) == [0, 5, 5, 5 + 4095 // 2, 4100, 4200, 4200 + 5800 // 3,
                             4200 + 2 * 5800 // 3, 10000]
     assert np.all(np.diff(capped) <= 2048) and np.all(np.diff(capped) >= 0)
+
+
+def _block_brute_force(sets, col):
+    """Validity and the first-fit property of a block colouring."""
+    S = [set(int(r) for r in w) for w in sets]
+    for b in range(len(S)):
+        for d in range(len(S)):
+            if d != b and S[b] & S[d]:
+                assert col[b] != col[d], (b, d)
+        earlier = {col[d] for d in range(b) if S[b] & S[d]}
+        for k in range(col[b]):
+            assert k in earlier, (b, k)
+
+
+def test_block_colouring_brute_force():
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        nb = int(rng.integers(1, 40))
+        sets = [rng.choice(60, size=int(rng.integers(0, 6)), replace=False) for _ in range(nb)]
+        col, nc = R.color_blocks(sets)
+        _block_brute_force(sets, col)
+        assert nc == (col.max() + 1 if nb else 0)
+
+
+def test_block_colouring_closed_forms():
+    # disjoint sets: one class; a chain where only neighbours overlap: two
+    # alternating classes; one shared row: every block its own class
+    col, nc = R.color_blocks([[3 * b, 3 * b + 1] for b in range(10)])
+    assert nc == 1 and not col.any()
+    col, nc = R.color_blocks([[b, b + 1] for b in range(10)])
+    assert nc == 2 and np.array_equal(col, np.arange(10) % 2)
+    col, nc = R.color_blocks([[5, 100 + b] for b in range(7)])
+    assert nc == 7 and np.array_equal(col, np.arange(7))
+    assert R.color_blocks([])[1] == 0
+
+
+@pytest.mark.parametrize("make", SMALL[:4])
+def test_block_colouring_of_single_rows_is_row_colouring(make):
+    """With one row per block and its write set W(i), the block colouring is
+    the greedy row colouring of Sec. 3.2 (pinned above by brute force)."""
+    c = csrc_of(make())
+    sets = [R.write_set(c, i) for i in range(c["n"])]
+    col, nc = R.color_blocks(sets)
+    ref, nref = R.color(c, R.WRITE_SET)
+    assert np.array_equal(col, ref) and nc == nref
