@@ -15,9 +15,11 @@ plain FP64 kernel (one thread per row, global atomics) is timed the same way
 as the baseline.  Prints one JSON line.
 
 Other workloads: hex100_random / hex100_rcm (the same mesh renumbered),
-tet80 (3-dof tetrahedral mesh, for the reduced-precision forms) and batch256
-(256 matrices of uneven size with 1..32 right-hand sides each, run as one
-persistent launch under a HIP graph).
+tet80 (3-dof tetrahedral mesh, for the reduced-precision forms), hex100_sym
+(numerically symmetric values, one stored value array), rect100 (the mesh
+plus overlap couplings, n x m, A_S + A_R) and batch256 (256 matrices of
+uneven size with 1..32 right-hand sides each, run as one persistent launch
+under a HIP graph).
 """
 
 import argparse
@@ -186,6 +188,88 @@ def cpu_baseline(host, x, budget_s=12.0):
         reps += 1
     dt = (time.perf_counter() - t0) / reps
     return reps, dt
+
+
+def bench_rect(args):
+    """Rectangular matrices A = A_S + A_R (Sec. 2.1, Fig. 2b): the 27-point
+    mesh of side^3 nodes plus couplings of its top face to side^2 overlap
+    nodes (n x m, m = n + side^2).  A step is y = A x (x of m values) then
+    y = A^T x (y of m values) on the next rotated copy; the square part runs
+    under the given plan (default PRIVATE, atomic merge, 8192/256)."""
+    import torch
+    import paper_1003_0952_amd as C
+    from synth import workloads as W
+    from oracle import reference as R
+    side = int(args.workload[4:] or 100)
+    (n, m, rowptr, col, val), x = W.rect_mesh(side)
+    (srp, scol, sval), r = C.csrc_rect_split(n, m, rowptr, col, val)
+    host = C.csrc_from_csr(n, srp, scol, sval)
+    k, kr = host["k"], r["kr"]
+    vb = {"f64": 8, "f32": 4, "bf16": 2}[args.dtype]
+    xb = 8 if args.dtype == "f64" else 4
+    # square part (x and y of n values) plus A_R (iar, jar, ar) and the m - n
+    # overlap values of x (or of y for the transpose)
+    B1 = algorithmic_bytes(n, k, vb, xb, xb) + 4 * (n + 1) + kr * (4 + vb) + (m - n) * xb
+    ncopy = args.copies or max(2, math.ceil(3 * MALL_BYTES / B1))
+    mats = [C.Matrix(host, args.dtype) for _ in range(ncopy)]
+    rps = [C.RectPart(r, args.dtype) for _ in range(ncopy)]
+    if args.variant == "auto":
+        vname, vkw = "private", {"tile_work": args.tile_work or 8192, "block": args.block or 256, "atomic_merge": 1}
+    else:
+        vname = args.variant
+        vkw = {k_: v_ for k_, v_ in (("tile_work", args.tile_work), ("block", args.block),
+                                     ("atomic_merge", args.atomic_merge)) if v_}
+    plans = [C.Plan(A_, vname, **vkw) for A_ in mats]
+    xd = mats[0].xdtype
+    xs = [torch.from_numpy(x).to("cuda", xd) for _ in range(ncopy)]
+    xts = [torch.from_numpy(x[:n]).to("cuda", xd) for _ in range(ncopy)]
+    ys = [torch.empty(n, dtype=plans[0].ytorch, device="cuda") for _ in range(ncopy)]
+    yts = [torch.empty(m, dtype=plans[0].ytorch, device="cuda") for _ in range(ncopy)]
+
+    def step(s_):
+        c = s_ % ncopy
+        C.csrc_spmv_rect(mats[c], rps[c], plans[c], xs[c], ys[c])
+        C.csrc_spmv_rect_t(mats[c], rps[c], plans[c], xts[c], yts[c])
+
+    for s_ in range(args.warmup):
+        step(s_)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for s_ in range(args.steps):
+        step(s_)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    c0 = R.csr_to_csrc(n, srp, scol, sval)
+    step(0)
+    torch.cuda.synchronize()
+
+    def rel(a_, b_):
+        return float(np.max(np.abs(a_ - b_)) / np.max(np.abs(b_)))
+
+    err = max(rel(ys[0].double().cpu().numpy(), R.spmv_rect(c0, r, x)),
+              rel(yts[0].double().cpu().numpy(), R.spmv_rect_t(c0, r, x[:n])))
+    gbs = 2 * B1 / (ms * 1e-3) / 1e9
+    nnz = 2 * k + n + kr
+    out = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"rect{side}_27pt_{args.dtype}", "n": n, "m": m, "nnz": nnz, "k": k, "kr": kr,
+                   "variant": vname, **vkw, "copies": ncopy,
+                   "step": "y=(A_S+A_R)x then y=(A_S+A_R)^T x on the next rotated copy"},
+        "gflops": round(2 * (2 * (nnz - n) + n) / (ms * 1e-3) / 1e9, 1),
+        "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "max_rel_err_vs_oracle": err,
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "one product = the square product's launches + k_rect_gather (or fill + k_rect_scatter)",
+                     "bytes_per_launch": B1, "duration_us": round(ms / 2 * 1e3, 2)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
 
 
 BATCH_COUNT = 256
@@ -367,6 +451,9 @@ def main():
 
     if args.workload.startswith("batch"):
         bench_batch(args)
+        return
+    if args.workload.startswith("rect"):
+        bench_rect(args)
         return
 
     import torch

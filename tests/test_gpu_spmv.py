@@ -185,3 +185,42 @@ def test_tile_colour_classes(torch_cuda, case, tile_work):
             assert info["ncolors"] > 2, info
         y2, _ = run(torch, C, host, x, "tile_color", transpose, tile_work=tile_work)
         assert rel_inf(y, y2) <= 1e-15, (name, tile_work, transpose)
+
+
+@pytest.mark.parametrize("tile_work", [300, 8192, 1 << 20])
+def test_atomic_merge_repeated(torch_cuda, tile_work):
+    """PRIVATE with the atomic merge clears y before adding into it.
+    Repeated products on one workspace (A x, A^T x and the two-product
+    call), y filled with NaN before each, stay bit-exact on integer data (a
+    value left uncleared would stay NaN), and afterwards the workspace is
+    byte-for-byte what the upload wrote (the product writes no plan state).
+    Tile sizes give many tiles and a single tile."""
+    import paper_1003_0952_amd as C
+    from synth import workloads as W
+    torch = torch_cuda
+    cases = [c for c in INT_CASES if c[0] in ("hex17_natural", "banded7001", "powerlaw6000", "n1")]
+    a40, x40 = W.hex_mesh(40, "natural", kind="int")
+    cases.append(("hex40_natural", a40, x40))
+    for name, a, x in cases:
+        print(f"case {name} atomic merge repeated, tile_work {tile_work}", flush=True)
+        c = oracle_csrc(a)
+        ref, reft = R.spmv(c, x), R.spmv_t(c, x)
+        host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+        A = C.Matrix(host, "f64")
+        plan = C.Plan(A, "private", atomic_merge=1, tile_work=tile_work)
+        before = plan.workspace.clone()
+        xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", A.xdtype)
+        y = torch.empty((A.n,), dtype=plan.ytorch, device="cuda")
+        yt = torch.empty_like(y)
+        for rep in range(6):
+            y.fill_(float("nan"))
+            yt.fill_(float("nan"))
+            if rep % 3 == 2:
+                C.csrc_spmv_pair(A, plan, xt, y, yt)
+            else:
+                C.csrc_spmv(A, plan, xt, y)
+                C.csrc_spmv_t(A, plan, xt, yt)
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy(), ref), (name, tile_work, rep)
+            assert np.array_equal(yt.cpu().numpy(), reft), (name, tile_work, rep)
+        assert torch.equal(plan.workspace, before), (name, tile_work)
