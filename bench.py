@@ -299,7 +299,7 @@ def bench_batch(args):
         A = C.Matrix(host, args.dtype)
         mats.append(A)
         Xs.append(torch.from_numpy(X).to("cuda", A.xdtype))
-        members.append((host, X))
+        members.append((a, X))
         r = X.shape[1]
         B1 += algorithmic_bytes(host["n"], host["k"], vb, xb, xb, r)
         F1 += flops(host["n"], host["k"], r)
@@ -359,8 +359,8 @@ def bench_batch(args):
         C.BatchPlan.launch_graph(gg)
         torch.cuda.synchronize()
         for i in sample:
-            host, X = members[i]
-            c = {kk: host[kk] for kk in ("n", "k", "ia", "ja", "ad", "al", "au")}
+            a, X = members[i]
+            c = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
             f = R.spmv_t if tr else R.spmv
             ref = np.stack([f(c, np.ascontiguousarray(X[:, j])) for j in range(X.shape[1])], axis=1)
             got = Ys[i].double().cpu().numpy()
@@ -369,24 +369,32 @@ def bench_batch(args):
 
     cpu = None
     if not args.no_cpu:
-        # oracle on the leading members until the time budget is spent
-        t0 = time.perf_counter()
+        # passes over the members until about 12 s of products (only the
+        # products are timed, not the oracle's own CSRC split)
+        dt = 0.0
         done_b = 0
         done_m = 0
-        for i in range(BATCH_COUNT):
-            host, X = members[i]
-            c = {kk: host[kk] for kk in ("n", "k", "ia", "ja", "ad", "al", "au")}
-            for j in range(X.shape[1]):
-                xj = np.ascontiguousarray(X[:, j])
-                R.spmv(c, xj)
-                R.spmv_t(c, xj)
-            done_b += 2 * algorithmic_bytes(host["n"], host["k"], vb, xb, xb, X.shape[1])
-            done_m += 1
-            if time.perf_counter() - t0 > 12.0:
-                break
-        dt = time.perf_counter() - t0
+        split = {}
+        while dt <= 12.0:
+            for i in range(BATCH_COUNT):
+                a, X = members[i]
+                if i not in split:
+                    split[i] = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+                c = split[i]
+                t0 = time.perf_counter()
+                for j in range(X.shape[1]):
+                    xj = np.ascontiguousarray(X[:, j])
+                    R.spmv(c, xj)
+                    R.spmv_t(c, xj)
+                dt += time.perf_counter() - t0
+                done_b += 2 * algorithmic_bytes(c["n"], c["k"], vb, xb, xb, X.shape[1])
+                done_m += 1
+                if dt > 12.0:
+                    break
+        del split
         cpu = {"value": round(done_b / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"members 0..{done_m - 1} of the batch, every right-hand side, y=Ax and y=A^T x, "
+               "sample": f"{done_m} members in batch order ({done_m / BATCH_COUNT:.2f} passes over the batch), "
+                         f"every right-hand side, y=Ax and y=A^T x, "
                          f"plain sequential C oracle (FP64 values), {dt:.1f} s"}
 
     gbs = 2 * B1 / (ms * 1e-3) / 1e9
@@ -573,8 +581,9 @@ def main():
 
     # parity spot check of the timed configuration against the oracle (and of
     # the pair call, when timed)
+    # (the oracle splits the CSR input itself: no oracle input comes from the library)
     from oracle import reference as R
-    c0 = {kk: host[kk] for kk in ("n", "k", "ia", "ja", "ad", "al", "au")}
+    c0 = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
     ry = R.spmv(c0, x)
     ryt = R.spmv_t(c0, x)
 
@@ -593,7 +602,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        reps, dt = cpu_baseline(host, x)
+        reps, dt = cpu_baseline(c0, x)
         cpu = {"value": round(2 * B1 / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"full {args.workload} matrix, {reps} steps (y=Ax and y=A^T x each), "
                          f"plain sequential C oracle, {dt*1e3:.1f} ms/step",

@@ -1,0 +1,290 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations the
+benchmark times (every candidate of its tuner, and the batched launch).
+
+* hex100: 27-point hexahedral mesh of 100^3 nodes, n = 10^6, 26,463,592
+  stored entries, FP64.  Natural numbering: every tuner candidate, y = A x
+  and y = A^T x, relative infinity-norm error <= 1e-12 against the FP64
+  oracle, the two-product call, and integer-valued data bit-exact.  Random
+  and RCM numberings, numerically symmetric values and the rectangular form
+  (A_S + A_R) in the configurations the benchmark picks for them.
+* tet80: Kuhn tetrahedral mesh, 80^3 nodes, 3 dofs per node, n = 1,536,000,
+  67,746,222 stored entries: FP64 within 1e-12; FP32 and BF16 storage within
+  the accumulation bound of the oracle on the stored values and within the
+  stated total bound of the FP64 oracle.
+* batch256: the 256-matrix batch (1..32 right-hand sides each) from one graph
+  launch per product kind, sampled members checked column by column.
+
+The oracle splits every CSR input itself (no oracle input comes from the
+library) and whole output vectors are compared: the sequential C oracle takes
+milliseconds per product at these sizes.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import reference as R
+from synth import workloads as W
+from tests.helpers import oracle_csrc, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+UNSUPPORTED = -9
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1003_0952_amd as C
+    from paper_1003_0952_amd import tuner as T
+    assert torch.cuda.is_available()
+    return torch, C, T
+
+
+def product(torch, C, A, plan, xt, transpose):
+    y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+    (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64)
+
+
+def candidate_plans(C, T, A):
+    """(name, plan) for every tuner candidate the matrix admits; the others
+    must be refused as unsupported (the tuner then skips them)."""
+    out = []
+    for i, (v, kw) in enumerate(T.CANDIDATES):
+        try:
+            out.append((T.candidate_name(i), C.Plan(A, v, **kw)))
+        except C.CsrcError as e:
+            assert e.status == UNSUPPORTED, (T.candidate_name(i), e.status)
+    return out
+
+
+def prepared(a, x, C):
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    return c, host, R.spmv(c, x), R.spmv_t(c, x)
+
+
+@pytest.fixture(scope="module")
+def hex100(lib):
+    torch, C, T = lib
+    a, x = W.hex_mesh(100, "natural")
+    print(f"hex100 natural: n={a.n} nnz={int(a.rowptr[-1])}", flush=True)
+    c, host, ry, ryt = prepared(a, x, C)
+    return a, x, c, host, ry, ryt
+
+
+def test_hex100_split_bit_exact(lib, hex100):
+    """The library's CSR -> CSRC split at full size equals the oracle's."""
+    a, x, c, host, _, _ = hex100
+    assert host["k"] == c["k"] == 12731796
+    for key in ("ia", "ja", "ad", "al", "au"):
+        assert np.array_equal(np.asarray(host[key]), np.asarray(c[key])), key
+
+
+def test_hex100_every_candidate(lib, hex100):
+    torch, C, T = lib
+    a, x, c, host, ry, ryt = hex100
+    A = C.Matrix(host, "f64")
+    xt = torch.from_numpy(x).to("cuda")
+    plans = candidate_plans(C, T, A)
+    assert len(plans) == len(T.CANDIDATES)
+    for name, plan in plans:
+        e = rel_inf(product(torch, C, A, plan, xt, False), ry)
+        et = rel_inf(product(torch, C, A, plan, xt, True), ryt)
+        print(f"hex100 {name}: Ax {e:.2e}  ATx {et:.2e}", flush=True)
+        assert e <= TOL and et <= TOL, name
+
+
+def test_hex100_pair(lib, hex100):
+    """Both products in one call, for the PRIVATE candidates."""
+    torch, C, T = lib
+    a, x, c, host, ry, ryt = hex100
+    A = C.Matrix(host, "f64")
+    xt = torch.from_numpy(x).to("cuda")
+    for name, plan in candidate_plans(C, T, A):
+        if not name.startswith("private"):
+            continue
+        y = torch.full((A.n,), float("nan"), dtype=torch.float64, device="cuda")
+        yt = torch.full_like(y, float("nan"))
+        C.csrc_spmv_pair(A, plan, xt, y, yt)
+        torch.cuda.synchronize()
+        e, et = rel_inf(y.cpu().numpy(), ry), rel_inf(yt.cpu().numpy(), ryt)
+        print(f"hex100 pair {name}: Ax {e:.2e}  ATx {et:.2e}", flush=True)
+        assert e <= TOL and et <= TOL, name
+
+
+def test_hex100_integer_bit_exact(lib):
+    """Integer values in [-8, 8]: every partial sum is an exact integer, so
+    every candidate must reproduce the oracle bit for bit at full size."""
+    torch, C, T = lib
+    a, x = W.hex_mesh(100, "natural", kind="int")
+    c, host, ry, ryt = prepared(a, x, C)
+    A = C.Matrix(host, "f64")
+    xt = torch.from_numpy(x).to("cuda")
+    for name, plan in candidate_plans(C, T, A):
+        print(f"hex100 int {name}", flush=True)
+        assert np.array_equal(product(torch, C, A, plan, xt, False), ry), name
+        assert np.array_equal(product(torch, C, A, plan, xt, True), ryt), name
+
+
+@pytest.mark.parametrize("ordering", ["random", "rcm"])
+def test_hex100_renumbered(lib, ordering):
+    """Random numbering leaves windows too wide for PRIVATE (refused as
+    unsupported; ATOMIC, OWNER, COLOR and PLAIN run it); RCM runs all."""
+    torch, C, T = lib
+    a, x = W.hex_mesh(100, ordering)
+    c, host, ry, ryt = prepared(a, x, C)
+    A = C.Matrix(host, "f64")
+    xt = torch.from_numpy(x).to("cuda")
+    plans = candidate_plans(C, T, A)
+    names = [nm for nm, _ in plans]
+    assert any(nm.startswith("atomic") for nm in names)
+    if ordering == "rcm":
+        assert len(plans) == len(T.CANDIDATES)
+    for name, plan in plans:
+        if name == "plain":
+            continue   # one thread per row: covered on the natural numbering
+        e = rel_inf(product(torch, C, A, plan, xt, False), ry)
+        et = rel_inf(product(torch, C, A, plan, xt, True), ryt)
+        print(f"hex100 {ordering} {name}: Ax {e:.2e}  ATx {et:.2e}", flush=True)
+        assert e <= TOL and et <= TOL, (ordering, name)
+
+
+def test_hex100_symmetric_values(lib):
+    """Numerically symmetric values stored once (au aliases al)."""
+    torch, C, T = lib
+    a, x = W.hex_mesh(100, "natural", kind="sym")
+    c, host, ry, ryt = prepared(a, x, C)
+    A = C.Matrix(host, "f64", symmetric=True)
+    xt = torch.from_numpy(x).to("cuda")
+    for kw in ({"tile_work": 8192, "block": 256, "atomic_merge": 1},
+               {"tile_work": 4096, "block": 256, "atomic_merge": 1},
+               {"tile_work": 8192, "block": 256}):
+        plan = C.Plan(A, "private", **kw)
+        e = rel_inf(product(torch, C, A, plan, xt, False), ry)
+        et = rel_inf(product(torch, C, A, plan, xt, True), ryt)
+        print(f"hex100 sym {kw}: Ax {e:.2e}  ATx {et:.2e}", flush=True)
+        assert e <= TOL and et <= TOL, kw
+
+
+def test_rect100(lib):
+    """A = A_S + A_R, n = 10^6 rows, m = n + 10^4 columns (the mesh plus
+    couplings of its top face to overlap nodes)."""
+    torch, C, T = lib
+    (n, m, rowptr, col, val), x = W.rect_mesh(100)
+    (srp, scol, sval), r = R.split_rect(n, m, rowptr, col, val)
+    c = R.csr_to_csrc(n, srp, scol, sval)
+    ry, ryt = R.spmv_rect(c, r, x), R.spmv_rect_t(c, r, x[:n])
+    (lsrp, lscol, lsval), lr = C.csrc_rect_split(n, m, rowptr, col, val)
+    host = C.csrc_from_csr(n, lsrp, lscol, lsval)
+    A = C.Matrix(host, "f64")
+    rp = C.RectPart(lr, "f64")
+    plan = C.Plan(A, "private", tile_work=8192, block=256, atomic_merge=1)
+    x_full = torch.from_numpy(x).to("cuda")
+    x_sq = torch.from_numpy(np.ascontiguousarray(x[:n])).to("cuda")
+    y = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    yt = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    C.csrc_spmv_rect(A, rp, plan, x_full, y)
+    C.csrc_spmv_rect_t(A, rp, plan, x_sq, yt)
+    torch.cuda.synchronize()
+    e, et = rel_inf(y.cpu().numpy(), ry), rel_inf(yt.cpu().numpy(), ryt)
+    print(f"rect100: Ax {e:.2e}  ATx {et:.2e}", flush=True)
+    assert e <= TOL and et <= TOL
+
+
+@pytest.fixture(scope="module")
+def tet80(lib):
+    torch, C, T = lib
+    a, x = W.tet_mesh(80)
+    print(f"tet80: n={a.n} nnz={int(a.rowptr[-1])}", flush=True)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    return a, x, c, host
+
+
+@pytest.mark.parametrize("tile", [(4096, 256), (8192, 256), (16384, 512)])
+def test_tet80_fp64(lib, tet80, tile):
+    torch, C, T = lib
+    a, x, c, host = tet80
+    A = C.Matrix(host, "f64")
+    xt = torch.from_numpy(x).to("cuda")
+    plan = C.Plan(A, "private", tile_work=tile[0], block=tile[1], atomic_merge=1)
+    e = rel_inf(product(torch, C, A, plan, xt, False), R.spmv(c, x))
+    et = rel_inf(product(torch, C, A, plan, xt, True), R.spmv_t(c, x))
+    print(f"tet80 f64 {tile}: Ax {e:.2e}  ATx {et:.2e}", flush=True)
+    assert e <= TOL and et <= TOL
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("tile", [(4096, 256), (8192, 256)])
+def test_tet80_reduced_precision(lib, tet80, dtype, tile):
+    """FP32 accumulation: |y - y~| <= gamma_m(2^-24) (|A~||x~|)_i + the FP32
+    rounding of y, against the oracle on the stored values; and the stated
+    total bound against the FP64 oracle on the original data."""
+    torch, C, T = lib
+    a, x, c, host = tet80
+    A = C.Matrix(host, dtype)
+    xt = torch.from_numpy(x).to("cuda", torch.float32)
+    plan = C.Plan(A, "private", tile_work=tile[0], block=tile[1], atomic_merge=1)
+    ov = {s: R.dequantize(c[s], dtype) for s in ("ad", "al", "au")}
+    xf = R.to_f32(x).astype(np.float64)
+    uv = R.UNIT_ROUNDOFF[dtype]
+    m = R.row_terms(c)
+    for transpose in (False, True):
+        y = product(torch, C, A, plan, xt, transpose)
+        f = R.spmv_t if transpose else R.spmv
+        ref_stored = f(c, xf, **ov)
+        bound = R.accumulation_bound(c, xf, 2.0**-24, transpose, **ov) + 2.0**-24 * np.abs(ref_stored)
+        assert np.all(np.abs(y - ref_stored) <= bound), (dtype, tile, transpose)
+        ref64 = f(c, x)
+        total = (uv + 2.0**-24 + R.gamma(m + 1, 2.0**-24) * (1 + uv) * (1 + 2.0**-24)) * \
+            R.abs_product(c, x, transpose)
+        assert np.all(np.abs(y - ref64) <= total), (dtype, tile, transpose)
+        print(f"tet80 {dtype} {tile} T={transpose}: vs stored {rel_inf(y, ref_stored):.2e}, "
+              f"vs fp64 {rel_inf(y, ref64):.2e}", flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch256(lib, dtype):
+    """The 256-matrix batch in the tile shape the benchmark's tuner picks for
+    it, both graphs launched once; sampled members checked per column."""
+    torch, C, T = lib
+    members, mats, Xs = [], [], []
+    for i in range(256):
+        a, X = W.batch_member(i)
+        host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+        A = C.Matrix(host, dtype)
+        members.append((a, X))
+        mats.append(A)
+        Xs.append(torch.from_numpy(X).to("cuda", A.xdtype))
+    rs = [X.shape[1] for _, X in members]
+    kw = {"tile_work": 16384, "block": 512} if dtype == "f64" else {"tile_work": 8192, "block": 512}
+    ydt = "f64" if dtype == "f64" else "f32"
+    bp = C.BatchPlan(mats, rs, ydtype=ydt, **kw)
+    Ys = [torch.empty((A.n, r), dtype=bp.ytorch, device="cuda") for A, r in zip(mats, rs)]
+    bp.bind(Xs, Ys)
+    largest = max(range(256), key=lambda i: mats[i].n)
+    sample = sorted(set(range(0, 256, 16)) | {255, largest})
+    for transpose in (False, True):
+        for Y in Ys:
+            Y.fill_(float("nan"))
+        C.BatchPlan.launch_graph(bp.graph(transpose))
+        torch.cuda.synchronize()
+        for i in sample:
+            a, X = members[i]
+            c = oracle_csrc(a)
+            f = R.spmv_t if transpose else R.spmv
+            got = Ys[i].double().cpu().numpy()
+            if dtype == "f64":
+                ref = np.stack([f(c, np.ascontiguousarray(X[:, j])) for j in range(X.shape[1])], axis=1)
+                assert rel_inf(got, ref) <= TOL, (i, transpose)
+            else:
+                ov = {s: R.dequantize(c[s], "f32") for s in ("ad", "al", "au")}
+                for j in range(X.shape[1]):
+                    xf = R.to_f32(X[:, j]).astype(np.float64)
+                    ref = f(c, xf, **ov)
+                    bound = R.accumulation_bound(c, xf, 2.0**-24, transpose, **ov) + 2.0**-24 * np.abs(ref)
+                    assert np.all(np.abs(got[:, j] - ref) <= bound), (i, j, transpose)
+        print(f"batch256 {dtype} T={transpose}: {len(sample)} members checked", flush=True)
