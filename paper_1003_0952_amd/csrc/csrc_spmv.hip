@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "device_common.h"
 #include "internal.h"
@@ -395,26 +396,33 @@ __device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT, NP> &
 
 // Stream entries [kb, k1) of E (kb = k0 rounded down to even).  `cur` holds
 // the first batch, issued by the caller before its staging; each batch is
-// processed while the next one loads.  The batch loop runs the same number
-// of times in every lane (lanes past k1 see only kNoRow), so after_first()
-// is called once, by all lanes together, after the first batch.
+// processed while the next one loads.  The two batches alternate roles (the
+// loop is unrolled by two), so no batch is copied between registers.  The
+// batch loop runs the same number of times in every lane (lanes past k1 see
+// only kNoRow), so after_first() is called once, by all lanes together,
+// after the first batch.
 template <class VT, bool LOAD_AU, bool NT, int NP, class NeedAu, class Ent, class Flush, class Hook = NoHook>
 __device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT, NP> &cur, const Entries<VT, NT> &E,
                                            const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
                                            NeedAu need_au, Ent ent, Flush flush, Hook after_first = Hook())
 {
-    const int half = 2 * (int)blockDim.x;
+    const int step = NP * 2 * (int)blockDim.x;
     const int kb = E.kb, k1 = E.ke;
+    Batch<VT, true, LOAD_AU, NT, NP> nxt;
     int base = kb;
-    do {
-        const int qb = base + 2 * (int)threadIdx.x;
-        Batch<VT, true, LOAD_AU, NT, NP> nxt;
-        if (base + NP * half < k1) nxt.load(qb + NP * half, E);
-        process_batch<VT, LOAD_AU, NT>(cur, qb, E, s_rid, s_x, need_au, ent, flush);
+    for (;;) {
+        const int qa = base + 2 * (int)threadIdx.x;
+        if (base + step < k1) nxt.load(qa + step, E);
+        process_batch<VT, LOAD_AU, NT>(cur, qa, E, s_rid, s_x, need_au, ent, flush);
         if (base == kb) after_first();
-        cur = nxt;
-        base += NP * half;
-    } while (base < k1);
+        base += step;
+        if (base >= k1) break;
+        const int qc = base + 2 * (int)threadIdx.x;
+        if (base + step < k1) cur.load(qc + step, E);
+        process_batch<VT, LOAD_AU, NT>(nxt, qc, E, s_rid, s_x, need_au, ent, flush);
+        base += step;
+        if (base >= k1) break;
+    }
 }
 
 // Stage a tile's own rows: s_x[i] = x_i and s_y[i] = ad_i x_i (the diagonal
@@ -636,7 +644,11 @@ struct NextTile {
 // slot offsets sit in scalar registers (read from the lanes of a NextTile
 // that hold them) and the slot is found by compares, without LDS traffic;
 // otherwise by a binary search over the LDS copy of the interval list.
+// NC > 1 is the most intervals the caller has checked the tile to have (at
+// most kRegIntervals): the compares stop there.
+template <int NC = kRegIntervals>
 struct WindowMap {
+    static_assert(NC > 1 && NC <= kRegIntervals, "compares over the record's intervals");
     int n;
     i8v row, off;   // vector types keep the table in registers
     const int32_t *s_ivrow, *s_ivslot;
@@ -653,10 +665,10 @@ struct WindowMap {
 
     __device__ __forceinline__ int slot(int j) const
     {
-        if (n <= kRegIntervals) {
+        if (NC < kRegIntervals || n <= kRegIntervals) {
             int o = off[0];
 #pragma unroll
-            for (int k = 1; k < kRegIntervals; ++k) o = j >= row[k] ? off[k] : o;
+            for (int k = 1; k < NC; ++k) o = j >= row[k] ? off[k] : o;
             return j + o;
         }
         const int k = upper_index(s_ivrow, n, j);
@@ -684,7 +696,9 @@ constexpr int kPrivatePairs = 2;
 
 constexpr int kMergePass = 0, kMergeAtomic = 1, kMergeColor = 2;
 
-template <class VT, class YT, int MODE>
+// NC: the plan's largest number of window intervals of one tile is at most
+// NC (2, 4 or kRegIntervals): the window lookup makes NC - 1 compares.
+template <class VT, class YT, int MODE, int NC = kRegIntervals>
 __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__restrict__ tlist,
                                                  const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
@@ -718,11 +732,11 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__res
     nt.window(x);
     nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
     const int r0 = nt.r0, T = nt.T, W = nt.W;
-    WindowMap wm;
-    wm.init(nt, s_ivrow);
     __syncthreads();
     settle_loads();
 
+    WindowMap<NC> wm;
+    wm.init(nt, s_ivrow);
     auto ent = [&, wm](int j, A w) -> A {
         const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
         atomic_add(&s_y[idx], w);
@@ -838,7 +852,7 @@ __global__ __launch_bounds__(512) void k_private_pair(PlanDev P, const int32_t *
     nt.window(x);
     nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
     const int r0 = nt.r0, T = nt.T, W = nt.W, k1 = nt.k1;
-    WindowMap wm;
+    WindowMap<> wm;
     wm.init(nt, s_ivrow);
     __syncthreads();
     // the transpose has the same diagonal: its sums start as those of y
@@ -1788,6 +1802,17 @@ static int device_cus();
 // longer workgroups clear a large y fastest)
 static int fill_grid(int64_t count) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (count + 4095) / 4096)); }
 
+// The PRIVATE tile kernel for a plan: numerically symmetric storage (au is
+// al) loads one value per entry; the window lookup makes as few compares as
+// the plan's largest interval count per tile allows.
+template <class VT, class YT, int MODE>
+static decltype(&k_private<VT, YT, MODE>) private_kernel(const csrc_plan *p, bool sym)
+{
+    if (p->max_intervals <= 2) return sym ? k_private<SymT<VT>, YT, MODE, 2> : k_private<VT, YT, MODE, 2>;
+    if (p->max_intervals <= 4) return sym ? k_private<SymT<VT>, YT, MODE, 4> : k_private<VT, YT, MODE, 4>;
+    return sym ? k_private<SymT<VT>, YT, MODE> : k_private<VT, YT, MODE>;
+}
+
 template <class VT, class YT, int G>
 static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *al_, const void *au_,
                           const void *x_, int64_t ldx, void *y_, int64_t ldy, int r, void *ws, hipStream_t s)
@@ -1850,12 +1875,12 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
             } else if (p->o.atomic_merge) {
                 k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
                 // numerically symmetric storage (au is al): one value load per entry
-                auto kern = al == au ? k_private<SymT<VT>, YT, kMergeAtomic> : k_private<VT, YT, kMergeAtomic>;
+                auto kern = private_kernel<VT, YT, kMergeAtomic>(p, al == au);
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
                 kern<<<p->ntiles, B, lds, s>>>(P, nullptr, A->ia, A->ja, ad, al, au, x, y, smax, emax);
                 return hip_status(hipGetLastError());
             } else {
-                auto kern = al == au ? k_private<SymT<VT>, YT, kMergePass> : k_private<VT, YT, kMergePass>;
+                auto kern = private_kernel<VT, YT, kMergePass>(p, al == au);
                 if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
                 kern<<<p->ntiles, B, lds, s>>>(P, nullptr, A->ia, A->ja, ad, al, au, x, y, smax, emax);
             }
@@ -1905,7 +1930,7 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         if (!single) return CSRC_ERR_UNSUPPORTED;
         const int emax = p->max_tile_entries, smax = p->max_span;
         const size_t lds = (size_t)lds_private(smax, emax, p->max_intervals, sizeof(Acc));
-        auto kern = al == au ? k_private<SymT<VT>, YT, kMergeColor> : k_private<VT, YT, kMergeColor>;
+        auto kern = private_kernel<VT, YT, kMergeColor>(p, al == au);
         if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
         k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
         // classes in ascending colour order
