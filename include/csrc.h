@@ -50,7 +50,9 @@ typedef enum csrc_status {
     CSRC_ERR_UNSUPPORTED = -9,     /* variant cannot run this matrix (e.g. the
                                       private windows exceed the LDS budget)      */
     CSRC_ERR_PLAN = -10,           /* plan does not match the matrix or call      */
-    CSRC_ERR_NOMEM = -11           /* host allocation failed                      */
+    CSRC_ERR_NOMEM = -11,          /* host allocation failed                      */
+    CSRC_ERR_NO_MODEL = -12        /* csrc_select without a trained network: the
+                                      caller tunes instead                        */
 } csrc_status;
 
 /* Human-readable name of a status code (static string, never NULL). */
@@ -504,6 +506,20 @@ int csrc_mlp_adam(int64_t count, float *params, const float *grads, float *m,
 int csrc_mlp_predict_host(int32_t hidden, int32_t classes, const float *params,
                           const float *mean, const float *scale,
                           const float *features, int32_t *cls);
+
+/*
+ * csrc_select -- the learned selector's pick for a matrix: the 12 features
+ * of csrc_features (the library colours the rows), then csrc_mlp_predict_host.
+ * ia/ja are HOST arrays (the structure of csrc_from_csr's output); params,
+ * mean and scale a trained network in host memory (the layout of
+ * csrc_mlp_param_count, 12 floats each for mean and scale).  *candidate is
+ * the class index, i.e. the position in the candidate list the network was
+ * trained on.  params == NULL returns CSRC_ERR_NO_MODEL without touching
+ * *candidate: exhaustive tuning is the fallback.  Errors: ARG, NOMEM.
+ */
+int csrc_select(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
+                int32_t hidden, int32_t classes, const float *params, const float *mean,
+                const float *scale, int32_t *candidate);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,7 @@ ERR_HIP = -8
 ERR_UNSUPPORTED = -9
 ERR_PLAN = -10
 ERR_NOMEM = -11
+ERR_NO_MODEL = -12
 
 F64, F32_, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32_, "bf16": BF16}
@@ -148,6 +149,7 @@ _sig("csrc_mlp_param_count", I64, [I32, I32])
 _sig("csrc_mlp_forward", ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P])
 _sig("csrc_mlp_backward", ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P, P])
 _sig("csrc_mlp_predict_host", ctypes.c_int, [I32, I32, P, P, P, P, P])
+_sig("csrc_select", ctypes.c_int, [I32, P, P, I32, I32, I32, P, P, P, P])
 _sig("csrc_mlp_adam", ctypes.c_int, [I64, P, P, P, P, I32, F32, F32, F32, F32, P])
 
 lib = _lib

@@ -41,6 +41,7 @@ extern "C" const char *csrc_status_string(int s)
     case CSRC_ERR_UNSUPPORTED: return "variant unsupported for this matrix";
     case CSRC_ERR_PLAN: return "plan does not match the call";
     case CSRC_ERR_NOMEM: return "host allocation failed";
+    case CSRC_ERR_NO_MODEL: return "no trained selector model";
     default: return "unknown status";
     }
 }
@@ -455,4 +456,16 @@ extern "C" int csrc_features(int32_t n, const int32_t *ia, const int32_t *ja, in
     } catch (const std::bad_alloc &) {
         return CSRC_ERR_NOMEM;
     }
+}
+
+extern "C" int csrc_select(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
+                           int32_t hidden, int32_t classes, const float *params, const float *mean,
+                           const float *scale, int32_t *candidate)
+{
+    if (!candidate) return CSRC_ERR_ARG;
+    if (!params) return CSRC_ERR_NO_MODEL;
+    float f[CSRC_NFEATURES];
+    const int st = csrc_features(n, ia, ja, vdtype, -1, f);
+    if (st != CSRC_OK) return st;
+    return csrc_mlp_predict_host(hidden, classes, params, mean, scale, f, candidate);
 }

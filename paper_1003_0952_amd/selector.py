@@ -123,6 +123,16 @@ class Selector:
                                           np_ptr(self.scale), np_ptr(f), ctypes.byref(c)), "predict")
         return c.value
 
+    def select(self, n, ia, ja, vdtype=B.F64):
+        """Class for a matrix structure (host ia/ja) through csrc_select:
+        the library computes the features and runs the network."""
+        ia = np.ascontiguousarray(ia, dtype=np.int32)
+        ja = np.ascontiguousarray(ja, dtype=np.int32)
+        c = ctypes.c_int32(0)
+        check(B.lib.csrc_select(n, np_ptr(ia), np_ptr(ja), vdtype, self.H, self.K, np_ptr(self.params),
+                                np_ptr(self.mean), np_ptr(self.scale), ctypes.byref(c)), "csrc_select")
+        return c.value
+
     def save(self, path=MODEL_PATH):
         with open(path, "w") as fh:
             json.dump({"hidden": self.H, "candidates": self.candidates, "params": self.params.tolist(),

@@ -80,3 +80,24 @@ def test_stored_features_are_the_library_features(stored, m):
     host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
     f = C.csrc_features(host["ia"], host["ja"], "f64", -1)
     assert np.allclose(f, rec["features"], rtol=1e-6)
+
+
+def test_csrc_select_matches_features_then_network(stored):
+    """csrc_select (library features + host network) picks the same class as
+    the two steps called one by one, and reports a missing model so the
+    caller can tune instead."""
+    import ctypes
+    from paper_1003_0952_amd import api as C, binding as B
+    from synth import workloads as W
+    _, model = stored
+    for a, _x in (W.quad64(), W.hex_mesh(17, "natural"), W.hex_mesh(17, "random"), W.tet_mesh(6)):
+        host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+        want = model.predict(C.csrc_features(host["ia"], host["ja"], "f64"))
+        assert model.select(host["n"], host["ia"], host["ja"]) == want
+    ia = np.ascontiguousarray(host["ia"], np.int32)
+    ja = np.ascontiguousarray(host["ja"], np.int32)
+    c = ctypes.c_int32(-5)
+    st = B.lib.csrc_select(host["n"], B.np_ptr(ia), B.np_ptr(ja), B.F64, model.H, model.K, None, None, None,
+                           ctypes.byref(c))
+    assert st == B.ERR_NO_MODEL and c.value == -5
+    assert b"model" in B.lib.csrc_status_string(st)
