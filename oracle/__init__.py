@@ -6,8 +6,9 @@ the GPU path computes, written from the paper (Batista, Ainsworth Jr. and
 Ribeiro, "Parallel structurally-symmetric sparse matrix-vector products on
 multi-core processors"):
 
-* ``reference``  CSR -> CSRC split (Sec. 2), the sequential product of Fig. 2a
-                 and its transpose (Sec. 5) via the C library, pure-Python
+* ``reference``  CSR -> CSRC split (Sec. 2), the sequential product from
+                 the splitting A = A_D + A_L + A_U and its transpose
+                 (Sec. 5) via the C library, pure-Python
                  loops for tiny cases, greedy colouring (Sec. 3.2), the
                  nnz-guided row partition and effective ranges (Sec. 3.1),
                  reduced-precision rounding and error bounds.

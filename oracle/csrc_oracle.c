@@ -20,28 +20,29 @@
 #include <string.h>
 
 /*
- * y = A x, following the sequential CSRC loop of Fig. 2a: row i forms
- * t = ad_i x_i + sum_k al_k x_{ja_k} in ascending k while adding au_k x_i into
- * y_{ja_k}; then y_i = t.  Every y_j with j < i was assigned at iteration j
- * before row i adds into it, so y needs no initialisation.
+ * y = A x from the splitting A = A_D + A_L + A_U of Sec. 2, one term after
+ * the other, each a plain loop over the stored entries in ascending order:
+ *   y   = A_D x          y_i  = ad_i x_i
+ *   y  += A_L x          y_i += al_q x_j   for the pair q = (i, j), j < i
+ *   y  += A_U x          y_j += au_q x_i   (au_q is a_ji, the mirror of q)
+ * The A_U term adds into earlier rows: this is the column-wise traversal of
+ * the upper part that CSRC implies.  Every y_i therefore sums, in this
+ * order, its diagonal term, its lower products in ascending column and the
+ * upper products of the later rows in ascending row.
  */
 void oracle_csrc_spmv(int32_t n, const int32_t *ia, const int32_t *ja,
                       const double *ad, const double *al, const double *au,
                       const double *x, double *y)
 {
-    for (int32_t i = 0; i < n; ++i) {
-        double xi = x[i];
-        double t = ad[i] * xi;
-        for (int32_t k = ia[i]; k < ia[i + 1]; ++k) {
-            int32_t j = ja[k];
-            t = t + al[k] * x[j];
-            y[j] = y[j] + au[k] * xi;
-        }
-        y[i] = t;
-    }
+    for (int32_t i = 0; i < n; ++i) y[i] = ad[i] * x[i];
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t q = ia[i]; q < ia[i + 1]; ++q) y[i] = y[i] + al[q] * x[ja[q]];
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t q = ia[i]; q < ia[i + 1]; ++q) y[ja[q]] = y[ja[q]] + au[q] * x[i];
 }
 
-/* y = A^T x: the same loop with the roles of al and au exchanged (Sec. 5). */
+/* y = A^T x: A^T = A_D + A_U^T + A_L^T, i.e. the same splitting with the
+ * roles of al and au exchanged (Sec. 5). */
 void oracle_csrc_spmv_t(int32_t n, const int32_t *ia, const int32_t *ja,
                         const double *ad, const double *al, const double *au,
                         const double *x, double *y)
@@ -50,24 +51,23 @@ void oracle_csrc_spmv_t(int32_t n, const int32_t *ia, const int32_t *ja,
 }
 
 /*
- * Y = A X for r right-hand sides stored row-major (X[i*ldx + c]): the Fig. 2a
- * loop applied to each column c in turn.
+ * Y = A X for r right-hand sides stored row-major (X[i*ldx + c]): the
+ * product above applied to each column c in turn.
  */
 void oracle_csrc_spmm(int32_t n, const int32_t *ia, const int32_t *ja,
                       const double *ad, const double *al, const double *au,
                       int32_t r, const double *X, int64_t ldx, double *Y, int64_t ldy)
 {
     for (int32_t c = 0; c < r; ++c) {
-        for (int32_t i = 0; i < n; ++i) {
-            double xi = X[(int64_t)i * ldx + c];
-            double t = ad[i] * xi;
-            for (int32_t k = ia[i]; k < ia[i + 1]; ++k) {
-                int32_t j = ja[k];
-                t = t + al[k] * X[(int64_t)j * ldx + c];
-                Y[(int64_t)j * ldy + c] = Y[(int64_t)j * ldy + c] + au[k] * xi;
-            }
-            Y[(int64_t)i * ldy + c] = t;
-        }
+#define XC(i) X[(int64_t)(i) * ldx + c]
+#define YC(i) Y[(int64_t)(i) * ldy + c]
+        for (int32_t i = 0; i < n; ++i) YC(i) = ad[i] * XC(i);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t q = ia[i]; q < ia[i + 1]; ++q) YC(i) = YC(i) + al[q] * XC(ja[q]);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t q = ia[i]; q < ia[i + 1]; ++q) YC(ja[q]) = YC(ja[q]) + au[q] * XC(i);
+#undef XC
+#undef YC
     }
 }
 

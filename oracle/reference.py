@@ -133,7 +133,7 @@ def csrc_to_dense(c):
 
 
 # --------------------------------------------------------------------------
-# Product (Fig. 2a) and transpose (Sec. 5)
+# Product (Sec. 2 splitting) and transpose (Sec. 5)
 # --------------------------------------------------------------------------
 
 def _vals(c, name, override):
@@ -142,7 +142,7 @@ def _vals(c, name, override):
 
 
 def spmv(c, x, **override):
-    """y = A x by the sequential CSRC loop (C oracle, FP64, no FMA)."""
+    """y = A x = (A_D + A_L + A_U) x, term by term (C oracle, FP64, no FMA)."""
     n = c["n"]
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.zeros(n, dtype=np.float64)
@@ -154,7 +154,7 @@ def spmv(c, x, **override):
 
 
 def spmv_t(c, x, **override):
-    """y = A^T x: Fig. 2a with al and au exchanged (Sec. 5)."""
+    """y = A^T x: the same splitting with al and au exchanged (Sec. 5)."""
     n = c["n"]
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.zeros(n, dtype=np.float64)
@@ -201,7 +201,7 @@ def split_rect(n, m, rowptr, col, val):
 
 
 def spmv_rect(c, r, x, **override):
-    """y = A x for A = A_S + A_R (Fig. 2b): the square CSRC loop on x[:n],
+    """y = A x for A = A_S + A_R (Fig. 2b): the square CSRC product on x[:n],
     then each row's auxiliary CSR entries gathered from the whole x."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     n = c["n"]
@@ -232,19 +232,21 @@ def spmv_rect_t(c, r, x, **override):
 
 
 def spmv_py(c, x, transpose=False):
-    """Pure-Python Fig. 2a loop (tiny inputs): same order as the C oracle."""
+    """Pure-Python product for tiny inputs, from A = A_D + A_L + A_U
+    (Sec. 2): the diagonal term, then every stored lower entry a_ij x_j into
+    y_i, then every mirrored upper entry a_ji x_i into y_j (same order and
+    rounding as the C oracle).  The transpose exchanges al and au (Sec. 5)."""
     n = c["n"]
     ia, ja, ad = c["ia"], c["ja"], c["ad"]
     al, au = (c["au"], c["al"]) if transpose else (c["al"], c["au"])
-    y = [0.0] * n
+    y = [float(ad[i]) * float(x[i]) for i in range(n)]
     for i in range(n):
-        xi = float(x[i])
-        t = float(ad[i]) * xi
+        for q in range(int(ia[i]), int(ia[i + 1])):
+            y[i] = y[i] + float(al[q]) * float(x[int(ja[q])])
+    for i in range(n):
         for q in range(int(ia[i]), int(ia[i + 1])):
             j = int(ja[q])
-            t = t + float(al[q]) * float(x[j])
-            y[j] = y[j] + float(au[q]) * xi
-        y[i] = t
+            y[j] = y[j] + float(au[q]) * float(x[i])
     return np.array(y)
 
 
@@ -340,11 +342,25 @@ def cap_rows(bounds, max_rows):
     return np.array(out, dtype=np.int64)
 
 
+def drop_empty(bounds):
+    """The non-empty blocks of a partition: boundaries with repeats removed.
+
+    (With more blocks than rows, or rows heavier than a block's share, the
+    partition has empty blocks; a GPU tile is a non-empty block.)
+    """
+    bounds = np.asarray(bounds, dtype=np.int64)
+    if bounds.shape[0] < 2:
+        return bounds
+    keep = np.concatenate([[True], bounds[1:] != bounds[:-1]])
+    return bounds[keep]
+
+
 def partition_for_target(ia, target, max_rows=2048):
-    """Partition with ceil(total work / target) blocks, then the row cap."""
+    """Partition with ceil(total work / target) blocks, then the row cap;
+    the tiles are the non-empty blocks."""
     total = int(row_weights(ia).sum())
     parts = max(1, -(-total // int(target)))
-    return cap_rows(partition(ia, parts), max_rows)
+    return drop_empty(cap_rows(partition(ia, parts), max_rows))
 
 
 def out_of_tile_targets(c, r0, r1):

@@ -110,6 +110,22 @@ def test_partition_weights_are_nnz():
     assert R.row_weights(c["ia"]).sum() == a.nnz
 
 
+def test_drop_empty_blocks():
+    """Tiles are the non-empty blocks: repeated boundaries go, the covered
+    rows and every non-empty block stay."""
+    assert list(R.drop_empty([0, 0, 3, 3, 3, 7, 9, 9])) == [0, 3, 7, 9]
+    assert list(R.drop_empty([0, 5])) == [0, 5]
+    c = csrc_of(P.banded(300, 40, 1.0, 3))
+    total = int(R.row_weights(c["ia"]).sum())
+    for target in (1, 10, 81, 500):
+        s = R.partition(c["ia"], max(1, -(-total // target)))
+        t = R.partition_for_target(c["ia"], target)
+        assert t[0] == 0 and t[-1] == c["n"] and np.all(np.diff(t) > 0)
+        assert set(t.tolist()) == set(R.cap_rows(s, 2048).tolist())
+    # one row per tile when the target is below every row's work
+    assert list(R.partition_for_target(c["ia"], 1)) == list(range(301))
+
+
 def test_out_of_tile_targets_brute_force():
     c = csrc_of(P.q1_hex(7, 7, 7))
     s = R.partition(c["ia"], 9)
