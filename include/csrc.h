@@ -153,8 +153,11 @@ typedef struct csrc_matrix {
 
 /*
  * Vector types.  FP64 storage uses FP64 x and y.  FP32/BF16 storage uses an
- * FP32 x, accumulates in FP32 and writes y as CSRC_F32 or CSRC_F64
- * (csrc_plan_opts.ydtype).
+ * FP32 x and writes y as CSRC_F32 or CSRC_F64 (csrc_plan_opts.ydtype).  Its
+ * products, per-lane row sums, window partials and the merge are FP32; the
+ * per-tile sums in LDS that receive the scattered upper products are FP64
+ * (gfx950 adds FP64 values in LDS at a far higher rate than FP32 ones), and
+ * are rounded to the output type when they leave the tile.
  */
 
 /* ------------------------------------------------------------ variants */
@@ -214,14 +217,9 @@ typedef struct csrc_plan_opts {
     int32_t compensated;      /* 1: compensated (TwoSum) accumulation of
                                  partial sums in the merge; reduced precision  */
     int32_t max_rhs;          /* largest r later passed to csrc_spmm (>= 1)   */
-    int32_t persistent;       /* PRIVATE, one right-hand side: 1 = persistent
-                                 workgroups that stream their tiles back to
-                                 back, staging tile t+1 while t streams (needs
-                                 block 512); 0 = one workgroup per tile       */
-    int32_t grid;             /* workgroups of the persistent launch (>= 8, one
-                                 tile range per XCD); 0 = as many as fit on
-                                 the device at once                           */
-    int32_t atomic_merge;     /* PRIVATE, one right-hand side, not persistent:
+    int32_t persistent;       /* reserved, must be 0 (CSRC_ERR_ARG otherwise) */
+    int32_t grid;             /* reserved, must be 0 (CSRC_ERR_ARG otherwise) */
+    int32_t atomic_merge;     /* PRIVATE, one right-hand side:
                                  1 = y is cleared and every tile adds its own
                                  rows and its window sums to y with global
                                  atomics (no partial buffer, no merge pass;
@@ -379,7 +377,8 @@ typedef struct csrc_batch_opts {
  * csrc_batch_plan_create -- plan for nmat independent products in one
  * persistent launch.  Per matrix m: n[m], host structure ia[m], ja[m] and
  * its number of right-hand sides r[m] (1..32).  The plan cuts every matrix
- * into owner tiles and orders the work list by decreasing cost.
+ * into PRIVATE tiles (local buffers of Sec. 3.1 in LDS) and orders the work
+ * list by decreasing cost.
  */
 int csrc_batch_plan_create(int32_t nmat, const int32_t *n,
                            const int32_t *const *ia, const int32_t *const *ja,
@@ -419,8 +418,8 @@ int csrc_spmv_t_batched(const csrc_batch_plan *plan, const csrc_matrix *A,
 typedef struct csrc_graph csrc_graph;   /* opaque: an instantiated HIP graph */
 
 /*
- * csrc_batch_graph_create -- build (not capture) a HIP graph whose single
- * kernel node is the batch launch of csrc_batch_run with these arguments;
+ * csrc_batch_graph_create -- build (not capture) a HIP graph whose kernel
+ * nodes are the launches of csrc_batch_run with these arguments, in order;
  * csrc_graph_launch replays it on a stream.  The workspace must stay bound.
  */
 int csrc_batch_graph_create(const csrc_batch_plan *plan, int32_t transpose,
@@ -520,6 +519,26 @@ int csrc_mlp_predict_host(int32_t hidden, int32_t classes, const float *params,
 int csrc_select(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
                 int32_t hidden, int32_t classes, const float *params, const float *mean,
                 const float *scale, int32_t *candidate);
+
+/* ------------------------------------------------------------ measurement */
+
+/*
+ * HBM ceiling probes (not part of the method): the rates that bound every
+ * product here, which is an HBM read stream with a small write side.  The
+ * paper states its products are bound by memory traffic (Sec. 4.1); these
+ * calls measure what this device's memory delivers to one kernel.
+ *
+ * csrc_stream_read -- read bytes (a multiple of 16) of device memory src
+ *   (16-byte aligned) with non-temporal 16-byte loads by grid workgroups of
+ *   256 threads; workgroup b writes a checksum word to sink[b] (device,
+ *   grid words), so no load can be dropped.  Asynchronous on stream.
+ * csrc_stream_copy -- copy bytes (a multiple of 16) from src to dst (both
+ *   16-byte aligned, not overlapping: CSRC_ERR_ALIAS) the same way.
+ * Errors: ARG (null, misaligned, bytes not a multiple of 16, grid outside
+ * 1..65536), ALIAS, HIP.
+ */
+int csrc_stream_read(const void *src, int64_t bytes, uint32_t *sink, int32_t grid, void *stream);
+int csrc_stream_copy(const void *src, void *dst, int64_t bytes, int32_t grid, void *stream);
 
 #ifdef __cplusplus
 }

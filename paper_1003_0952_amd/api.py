@@ -106,6 +106,59 @@ def csrc_features(ia, ja, vdtype="f64", ncolors=-1):
     return f
 
 
+# ------------------------------------------------------- argument checks
+#
+# The library receives raw device pointers and sizes; a tensor of the wrong
+# type, length, layout or device would make a kernel read or write past its
+# buffer.  Every wrapper below checks its tensors here, before any launch.
+
+def _same_device(t, dev, name):
+    import torch
+    want = torch.device(dev)
+    if t.device.type != want.type or (want.index is not None and t.device.index != want.index):
+        raise ValueError(f"{name} is on {t.device}, the matrix on {want}")
+
+
+def _vector(t, n, dtype, dev, name):
+    """t: a contiguous 1-D tensor of at least n elements of dtype on dev."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    _same_device(t, dev, name)
+
+
+def _block(t, n, r, dtype, dev, name):
+    """t: an n x r (or longer) row-major 2-D block of dtype on dev whose
+    columns are contiguous (stride(1) == 1) and rows at least r apart."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if t.dim() != 2 or t.shape[0] < n or t.shape[1] != r:
+        raise ValueError(f"{name} must be a 2-D block of at least {n} rows and exactly {r} columns, "
+                         f"got {tuple(t.shape)}")
+    if r > 0 and (t.stride(1) != 1 or t.stride(0) < r):
+        raise ValueError(f"{name} must be row-major with contiguous rows (stride(1) == 1, stride(0) >= r)")
+    _same_device(t, dev, name)
+
+
+def _xdtype(vdtype):
+    import torch
+    return torch.float64 if vdtype == B.F64 else torch.float32
+
+
+def _check_plan(A, plan):
+    if plan.n != A.n or plan.vdtype != A.vdtype:
+        raise ValueError("plan was made for another matrix (order or storage type differs)")
+
+
 # --------------------------------------------------------------- device side
 
 class Matrix:
@@ -174,7 +227,7 @@ class Plan:
 
     def __init__(self, A, variant="private", tile_work=0, lanes=0, block=0,
                  color_criterion=B.COLOR_WRITE_SET, ydtype="f32", compensated=False,
-                 max_rhs=1, persistent=0, grid=0, atomic_merge=0, stream=None):
+                 max_rhs=1, atomic_merge=0, stream=None):
         import torch
         self.variant = _variant(variant)
         opts = B.PlanOpts()
@@ -186,8 +239,6 @@ class Plan:
         opts.ydtype = _dt(ydtype)
         opts.compensated = 1 if compensated else 0
         opts.max_rhs = int(max_rhs)
-        opts.persistent = int(persistent)
-        opts.grid = int(grid)
         opts.atomic_merge = int(atomic_merge)
         h = ctypes.c_void_p(0)
         check(B.lib.csrc_plan_create(A.n, np_ptr(A.host_ia), np_ptr(A.host_ja), A.vdtype,
@@ -232,6 +283,9 @@ class Plan:
 
 def csrc_spmv(A, plan, x, y, stream=None):
     """y <- A x (overwrites y).  Asynchronous on the stream."""
+    _check_plan(A, plan)
+    _vector(x, A.n, _xdtype(A.vdtype), A.device, "x")
+    _vector(y, A.n, plan.ytorch, A.device, "y")
     check(B.lib.csrc_spmv(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y),
                           t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv")
     return y
@@ -239,6 +293,9 @@ def csrc_spmv(A, plan, x, y, stream=None):
 
 def csrc_spmv_t(A, plan, x, y, stream=None):
     """y <- A^T x (overwrites y).  Asynchronous on the stream."""
+    _check_plan(A, plan)
+    _vector(x, A.n, _xdtype(A.vdtype), A.device, "x")
+    _vector(y, A.n, plan.ytorch, A.device, "y")
     check(B.lib.csrc_spmv_t(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y),
                             t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_t")
     return y
@@ -247,6 +304,10 @@ def csrc_spmv_t(A, plan, x, y, stream=None):
 def csrc_spmv_pair(A, plan, x, y, yt, stream=None):
     """y <- A x and yt <- A^T x (one pass over the entries with a PRIVATE
     atomic-merge plan).  Asynchronous on the stream."""
+    _check_plan(A, plan)
+    _vector(x, A.n, _xdtype(A.vdtype), A.device, "x")
+    _vector(y, A.n, plan.ytorch, A.device, "y")
+    _vector(yt, A.n, plan.ytorch, A.device, "yt")
     check(B.lib.csrc_spmv_pair(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y), t_ptr(yt),
                                t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_pair")
     return y, yt
@@ -254,6 +315,11 @@ def csrc_spmv_pair(A, plan, x, y, yt, stream=None):
 
 def csrc_spmv_rect(A, R, plan, x, y, stream=None):
     """y (n) <- (A_S + A_R) x (m), Fig. 2b.  Asynchronous on the stream."""
+    _check_plan(A, plan)
+    if R.vdtype != A.vdtype or R.n != A.n:
+        raise ValueError("rectangular part does not match the matrix")
+    _vector(x, R.m, _xdtype(A.vdtype), A.device, "x")
+    _vector(y, A.n, plan.ytorch, A.device, "y")
     check(B.lib.csrc_spmv_rect(ctypes.byref(A.desc), ctypes.byref(R.desc), plan.handle, t_ptr(x), t_ptr(y),
                                t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_rect")
     return y
@@ -261,6 +327,11 @@ def csrc_spmv_rect(A, R, plan, x, y, stream=None):
 
 def csrc_spmv_rect_t(A, R, plan, x, y, stream=None):
     """y (m) <- (A_S + A_R)^T x (n).  Asynchronous on the stream."""
+    _check_plan(A, plan)
+    if R.vdtype != A.vdtype or R.n != A.n:
+        raise ValueError("rectangular part does not match the matrix")
+    _vector(x, A.n, _xdtype(A.vdtype), A.device, "x")
+    _vector(y, R.m, plan.ytorch, A.device, "y")
     check(B.lib.csrc_spmv_rect_t(ctypes.byref(A.desc), ctypes.byref(R.desc), plan.handle, t_ptr(x), t_ptr(y),
                                  t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)), "csrc_spmv_rect_t")
     return y
@@ -268,7 +339,10 @@ def csrc_spmv_rect_t(A, R, plan, x, y, stream=None):
 
 def csrc_spmm(A, plan, X, Y, stream=None):
     """Y <- A X for row-major n x r blocks (torch 2-D tensors, row stride = ld)."""
-    r = X.shape[1]
+    _check_plan(A, plan)
+    r = X.shape[1] if X.dim() == 2 else -1
+    _block(X, A.n, r, _xdtype(A.vdtype), A.device, "X")
+    _block(Y, A.n, r, plan.ytorch, A.device, "Y")
     check(B.lib.csrc_spmm(ctypes.byref(A.desc), plan.handle, r, t_ptr(X), X.stride(0), t_ptr(Y),
                           Y.stride(0), t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)),
           "csrc_spmm")
@@ -276,7 +350,11 @@ def csrc_spmm(A, plan, X, Y, stream=None):
 
 
 def csrc_spmm_t(A, plan, X, Y, stream=None):
-    r = X.shape[1]
+    """Y <- A^T X for row-major n x r blocks."""
+    _check_plan(A, plan)
+    r = X.shape[1] if X.dim() == 2 else -1
+    _block(X, A.n, r, _xdtype(A.vdtype), A.device, "X")
+    _block(Y, A.n, r, plan.ytorch, A.device, "Y")
     check(B.lib.csrc_spmm_t(ctypes.byref(A.desc), plan.handle, r, t_ptr(X), X.stride(0), t_ptr(Y),
                             Y.stride(0), t_ptr(plan.workspace), plan.ws_bytes, stream_ptr(stream)),
           "csrc_spmm_t")
@@ -340,6 +418,12 @@ class BatchPlan:
 
     def _arrays(self, Xs, Ys):
         m = len(self.mats)
+        if len(Xs) != m or len(Ys) != m:
+            raise ValueError(f"a batch of {m} matrices needs {m} X and {m} Y blocks")
+        xdt = _xdtype(self.vdtype)
+        for i, (A, r, X, Y) in enumerate(zip(self.mats, self.rs, Xs, Ys)):
+            _block(X, A.n, r, xdt, A.device, f"X[{i}]")
+            _block(Y, A.n, r, self.ytorch, A.device, f"Y[{i}]")
         descs = (B.CsrcMatrix * max(m, 1))(*[a.desc for a in self.mats])
         xp = (ctypes.c_void_p * max(m, 1))(*[t_ptr(x).value for x in Xs])
         yp = (ctypes.c_void_p * max(m, 1))(*[t_ptr(y).value for y in Ys])
@@ -385,3 +469,31 @@ def csrc_spmv_t_batched(bplan, Xs, Ys, stream=None):
     descs, xp, ldx, yp, ldy = bplan._arrays(Xs, Ys)
     check(B.lib.csrc_spmv_t_batched(bplan._h, descs, xp, np_ptr(ldx), yp, np_ptr(ldy), t_ptr(bplan.workspace),
                                     bplan.ws_bytes, stream_ptr(stream)), "csrc_spmv_t_batched")
+
+
+# -------------------------------------------------------------- measurement
+
+def csrc_stream_read(src, sink, grid=0, stream=None):
+    """Read the whole of device tensor src (non-temporal 16-byte loads);
+    sink: uint32 device tensor of at least grid words (default grid: 8
+    workgroups per compute unit)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if grid <= 0:
+        grid = 8 * torch.cuda.get_device_properties(src.device).multi_processor_count
+    if sink.dtype != torch.int32 or sink.numel() < grid or sink.device != src.device:
+        raise ValueError("sink must be an int32 tensor of at least grid elements on src's device")
+    check(B.lib.csrc_stream_read(t_ptr(src), nbytes, t_ptr(sink), int(grid), stream_ptr(stream)),
+          "csrc_stream_read")
+
+
+def csrc_stream_copy(src, dst, grid=0, stream=None):
+    """Copy device tensor src into dst (same byte size), non-temporal."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or dst.device != src.device:
+        raise ValueError("dst must have src's size and device")
+    if grid <= 0:
+        grid = 8 * torch.cuda.get_device_properties(src.device).multi_processor_count
+    check(B.lib.csrc_stream_copy(t_ptr(src), t_ptr(dst), nbytes, int(grid), stream_ptr(stream)),
+          "csrc_stream_copy")

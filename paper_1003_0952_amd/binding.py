@@ -151,6 +151,8 @@ _sig("csrc_mlp_backward", ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P, P, P, 
 _sig("csrc_mlp_predict_host", ctypes.c_int, [I32, I32, P, P, P, P, P])
 _sig("csrc_select", ctypes.c_int, [I32, P, P, I32, I32, I32, P, P, P, P])
 _sig("csrc_mlp_adam", ctypes.c_int, [I64, P, P, P, P, I32, F32, F32, F32, F32, P])
+_sig("csrc_stream_read", ctypes.c_int, [P, I64, P, I32, P])
+_sig("csrc_stream_copy", ctypes.c_int, [P, P, I64, I32, P])
 
 lib = _lib
 

@@ -464,7 +464,9 @@ extern "C" int csrc_select(int32_t n, const int32_t *ia, const int32_t *ja, int3
 {
     if (!candidate) return CSRC_ERR_ARG;
     if (!params) return CSRC_ERR_NO_MODEL;
-    if (!mean || !scale) return CSRC_ERR_ARG;   // before the features (which colour the rows)
+    // every argument is checked before the features, which colour the rows
+    // (seconds on a large matrix)
+    if (!mean || !scale || csrc_mlp_param_count(hidden, classes) < 0) return CSRC_ERR_ARG;
     float f[CSRC_NFEATURES];
     const int st = csrc_features(n, ia, ja, vdtype, -1, f);
     if (st != CSRC_OK) return st;

@@ -125,10 +125,9 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
     if (o.block != 0 && (o.block < 64 || o.block > 512 || o.block % 64)) return CSRC_ERR_ARG;
     if (o.lanes != 0 && (o.lanes < 1 || o.lanes > 64 || (o.lanes & (o.lanes - 1)))) return CSRC_ERR_ARG;
     if (o.tile_work < 0 || o.max_rhs < 0 || o.max_rhs > csrc::kMaxRhs) return CSRC_ERR_ARG;
-    if (o.persistent < 0 || o.persistent > 1 || o.grid < 0 || (o.grid > 0 && o.grid < 8)) return CSRC_ERR_ARG;
-    if (o.persistent && (o.variant != CSRC_V_PRIVATE || (o.block != 0 && o.block != 512))) return CSRC_ERR_ARG;
+    if (o.persistent != 0 || o.grid != 0) return CSRC_ERR_ARG;   // reserved fields
     if (o.atomic_merge < 0 || o.atomic_merge > 1) return CSRC_ERR_ARG;
-    if (o.atomic_merge && (o.variant != CSRC_V_PRIVATE || o.persistent || o.compensated)) return CSRC_ERR_ARG;
+    if (o.atomic_merge && (o.variant != CSRC_V_PRIVATE || o.compensated)) return CSRC_ERR_ARG;
     if (o.variant == CSRC_V_TILE_COLOR && o.max_rhs > 1) return CSRC_ERR_ARG;
     if (vdtype != CSRC_F64 && o.ydtype != CSRC_F32 && o.ydtype != CSRC_F64) return CSRC_ERR_ARG;
     *out = nullptr;
@@ -140,10 +139,9 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         p->vdtype = vdtype;
         p->o = o;
         if (p->o.block == 0)
-            // PRIVATE: 256 threads let six to eight tiles share a compute unit;
-            // the persistent schedule is written for 512
+            // PRIVATE: 256 threads let six to eight tiles share a compute unit
             p->o.block = (o.variant == CSRC_V_PLAIN || o.variant == CSRC_V_COLOR ||
-                          (o.variant == CSRC_V_PRIVATE && !o.persistent))
+                          o.variant == CSRC_V_PRIVATE)
                              ? 256
                              : 512;
         if (p->o.lanes == 0) p->o.lanes = auto_lanes(n, p->k);
@@ -162,6 +160,9 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             if (parts > (int64_t)1 << 30) { delete p; return CSRC_ERR_TOO_LARGE; }
             nnz_partition(n, ia, (int32_t)parts, p->tiles);
             cap_tile_rows(p->tiles, csrc::kMaxTileRows);
+            // a tile is a non-empty block (more blocks than rows, or rows
+            // heavier than a block's share, leave empty ones)
+            p->tiles.erase(std::unique(p->tiles.begin(), p->tiles.end()), p->tiles.end());
             p->ntiles = (int32_t)p->tiles.size() - 1;
             p->tile_k.resize(p->tiles.size());
             for (size_t t = 0; t < p->tiles.size(); ++t) p->tile_k[t] = ia[p->tiles[t]];
@@ -259,20 +260,6 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 }
             }
             p->lds_bytes = csrc::lds_private(p->max_span, p->max_tile_entries, p->max_intervals, acc);
-            if (p->o.persistent) {
-                // two staging buffers, rows and window intervals padded to
-                // 16-byte chunks; every tile's intervals fit its record
-                if (p->max_intervals > csrc::kRecIntervals) { delete p; return CSRC_ERR_UNSUPPORTED; }
-                const int32_t e = 16 / acc;
-                auto pad = [&](int32_t v) { return (v + e - 1) / e * e; };
-                for (const csrc::TileRec &r : p->trec) {
-                    int32_t sp = pad(r.r1 - r.r0);
-                    for (int k = 0; k < r.ni; ++k)
-                        sp += pad((k + 1 < r.ni ? r.ivslot[k + 1] : r.w) - r.ivslot[k]);
-                    p->max_span_padded = std::max(p->max_span_padded, sp);
-                }
-                p->lds_bytes = 2 * csrc::align16(csrc::lds_private_padded(p->max_span_padded, p->max_tile_entries, acc));
-            }
             if (p->o.max_rhs > 1)
                 p->lds_bytes = std::max(p->lds_bytes,
                                         csrc::lds_private_mm(p->max_span, p->max_tile_entries, p->max_intervals,

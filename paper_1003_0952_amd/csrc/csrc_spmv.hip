@@ -893,261 +893,6 @@ __global__ __launch_bounds__(512) void k_private_pair(PlanDev P, const int32_t *
     }
 }
 
-// ----------------------------------------------------- PRIVATE, persistent
-
-// PRIVATE with persistent workgroups.  XCD x (workgroups b = x mod 8) owns
-// the tile range [x ntiles / 8, (x+1) ntiles / 8), split into contiguous runs,
-// one per workgroup of that XCD.  A workgroup streams its run tile after
-// tile; two LDS buffers alternate.  While tile t streams out of one buffer:
-//   * the x values of tile t+1 (own rows, then each window interval padded
-//     to whole 16-byte chunks) are copied into the other buffer by LDS-direct
-//     buffer loads, which hold no registers;
-//   * its diagonal and row starts (row threadIdx.x) are loaded to registers;
-//   * its first batch of entries is loaded by the last batch step of tile t
-//     (two register batches alternate, so no copy forces an early wait).
-// At the switch every wave waits for its own copies but not for the batch in
-// flight, then the workgroup writes tile t out and sets tile t+1 up (sums,
-// row ids).  Per tile the arithmetic is that of k_private.
-constexpr int kPersistentBlock = 512;
-
-__device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t r, uint32_t off, void *lds_base)
-{
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds_base, 16, off, 0, 0,
-                                             0);
-}
-
-// Wait until at most n vector memory operations are outstanding (gfx9
-// encoding: vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left at maximum).
-template <int N>
-__device__ __forceinline__ void wait_vm()
-{
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
-// Vector memory operations of one Batch::load of all three arrays.
-template <class VT> struct BatchLoads { static constexpr int N = 6; };
-template <> struct BatchLoads<B16T> { static constexpr int N = 10; };
-
-// A tile of the persistent kernel: its record plus the LDS layout of its x
-// values: own rows at [0, T), window interval k at pos[k], each region padded
-// to a multiple of E values (one 16-byte chunk); span = end of the last one.
-template <int E>
-struct PTile {
-    int r0, T, k0, k1, kb, NI, W, span;
-    int64_t goff;
-    i8v row, slot, pos;
-
-    __device__ __forceinline__ void read(const PlanDev &P, int t)
-    {
-        const TileRec *R = P.trec + t;
-        r0 = R->r0;
-        T = R->r1 - r0;
-        k0 = R->k0;
-        k1 = R->k1;
-        kb = k0 & ~1;
-        NI = R->ni;
-        W = R->w;
-        goff = R->goff;
-        row = *reinterpret_cast<const i8v *>(R->ivrow);
-        slot = *reinterpret_cast<const i8v *>(R->ivslot);
-        int p = (T + E - 1) & ~(E - 1);
-#pragma unroll
-        for (int k = 0; k < kRegIntervals; ++k) {
-            pos[k] = p;
-            if (k < NI) {
-                const int end = k + 1 < NI ? slot[k + 1] : W;
-                p += (end - slot[k] + E - 1) & ~(E - 1);
-            }
-        }
-        span = p;
-    }
-
-    // LDS index of compact window slot sl
-    __device__ __forceinline__ int slot_index(int sl) const
-    {
-        int o = pos[0] - slot[0];
-#pragma unroll
-        for (int k = 1; k < kRegIntervals; ++k) o = sl >= slot[k] ? pos[k] - slot[k] : o;
-        return sl + o;
-    }
-    // LDS index of window column j
-    __device__ __forceinline__ int col_index(int j) const
-    {
-        int o = pos[0] - row[0];
-#pragma unroll
-        for (int k = 1; k < kRegIntervals; ++k) o = j >= row[k] ? pos[k] - row[k] : o;
-        return j + o;
-    }
-};
-
-template <class VT, class YT>
-__global__ __launch_bounds__(kPersistentBlock) void k_private_p(PlanDev P, int ntiles, int32_t n,
-                                                                const int32_t *__restrict__ ia,
-                                                                const int32_t *__restrict__ ja,
-                                                                const typename VT::V *__restrict__ ad,
-                                                                const typename VT::V *__restrict__ al,
-                                                                const typename VT::V *__restrict__ au,
-                                                                const typename VT::X *__restrict__ x,
-                                                                YT *__restrict__ y, int smax, int emax,
-                                                                int buf_bytes)
-{
-    using A = typename VT::A;
-    static_assert(sizeof(A) == sizeof(typename VT::X), "x is copied into LDS as is");
-    constexpr int E = 16 / sizeof(A);
-    constexpr int B = kPersistentBlock;
-    extern __shared__ __align__(16) unsigned char lds[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = B / 64;
-
-    // this workgroup's run of tiles
-    constexpr int X = 8;
-    const int xcd = blockIdx.x % X, slot = blockIdx.x / X;
-    const int nslot = ((int)gridDim.x - xcd + X - 1) / X;
-    const int lo = (int)((int64_t)xcd * ntiles / X), hi = (int)((int64_t)(xcd + 1) * ntiles / X);
-    const int ta = lo + (int)((int64_t)(hi - lo) * slot / nslot);
-    const int tb = lo + (int)((int64_t)(hi - lo) * (slot + 1) / nslot);
-    if (ta >= tb) return;
-
-    using S = typename VT::S;
-    auto bx = [&](int c) { return reinterpret_cast<A *>(lds + (size_t)c * buf_bytes); };
-    auto by = [&](int c) {
-        return reinterpret_cast<S *>(lds + (size_t)c * buf_bytes + align16((int64_t)smax * sizeof(A)));
-    };
-    auto brid = [&](int c) {
-        return reinterpret_cast<uint16_t *>(lds + (size_t)c * buf_bytes + lds_xs(smax, sizeof(A)));
-    };
-    const __amdgpu_buffer_rsrc_t rx = make_rsrc(x, (uint32_t)n * (uint32_t)sizeof(A));
-
-    // registers of the tile being staged: diagonal and row start of row tid
-    A nad = A(0);
-    int nq0 = 0, nq1 = 0;
-
-    // start tile u's staging into buffer c
-    auto stage_issue = [&](const PTile<E> &u, int c) {
-        A *sx = bx(c);
-        const int nco = (u.T + E - 1) / E;
-        for (int cb = wave * 64; cb < nco; cb += NW * 64) {
-            const int ch = cb + lane;
-            if (ch < nco) lds_copy16(rx, (uint32_t)(u.r0 + ch * E) * (uint32_t)sizeof(A), sx + cb * E);
-        }
-        const int w0 = u.pos[0], ncw = (u.span - w0) / E;
-        for (int cb = wave * 64; cb < ncw; cb += NW * 64) {
-            const int ch = cb + lane;
-            const int e = w0 + ch * E;    // LDS index of the chunk
-            int o = u.row[0] - u.pos[0];
-#pragma unroll
-            for (int k = 1; k < kRegIntervals; ++k) o = e >= u.pos[k] ? u.row[k] - u.pos[k] : o;
-            if (ch < ncw) lds_copy16(rx, (uint32_t)(e + o) * (uint32_t)sizeof(A), sx + w0 + cb * E);
-        }
-        if (tid < u.T) {
-            nad = (A)ldv(ad, u.r0 + tid);
-            nq0 = ia[u.r0 + tid];
-            nq1 = ia[u.r0 + tid + 1];
-        }
-    };
-    // tile u's sums and row ids in buffer c (its x values have landed)
-    auto stage_finish = [&](const PTile<E> &u, int c) {
-        const A *sx = bx(c);
-        S *sy = by(c);
-        uint16_t *rid = brid(c);
-        if (tid < u.T) {
-            sy[tid] = nad * sx[tid];
-            for (int q = nq0; q < nq1; ++q) rid[q - u.kb] = (uint16_t)tid;
-        }
-        for (int i = tid + B; i < u.T; i += B) {
-            sy[i] = (A)ldv(ad, u.r0 + i) * sx[i];
-            const int q1 = ia[u.r0 + i + 1];
-            for (int q = ia[u.r0 + i]; q < q1; ++q) rid[q - u.kb] = (uint16_t)i;
-        }
-        for (int i = u.T + tid; i < u.span; i += B) sy[i] = 0;
-        const int len = ((u.k1 - u.kb) + 3) & ~1;
-        for (int q = tid; q < u.k0 - u.kb; q += B) rid[q] = kNoRow;
-        for (int q = (u.k1 - u.kb) + tid; q < len; q += B) rid[q] = kNoRow;
-    };
-    auto write_out = [&](const PTile<E> &u, int c) {
-        const S *sy = by(c);
-        for (int i = tid; i < u.T; i += B) y[u.r0 + i] = (YT)sy[i];
-        if (u.W) {
-            A *part = reinterpret_cast<A *>(P.partials) + u.goff;
-            for (int sl = tid; sl < u.W; sl += B) part[sl] = (A)sy[u.slot_index(sl)];
-        }
-    };
-
-    // the streaming tile; of the next tile only its entry range is kept (its
-    // record is read again when it becomes current)
-    PTile<E> cu;
-    int nkb = 0, nk1 = 0;
-    auto issue_next = [&](int tn, int cn) {
-        PTile<E> u;
-        u.read(P, tn);
-        stage_issue(u, cn);
-        nkb = u.kb;
-        nk1 = u.k1;
-    };
-    int t = ta, c = 0;
-    cu.read(P, t);
-    stage_issue(cu, 0);
-    Batch<VT, true, true, true> bA, bB;
-    bA.load(cu.kb + 2 * tid, Entries<VT, true>(ja, al, au, cu.kb, cu.k1));
-    wait_vm<BatchLoads<VT>::N>();
-    __syncthreads();
-    stage_finish(cu, 0);
-    __syncthreads();
-    bool more = t + 1 < tb;
-    if (more) issue_next(t + 1, 1);
-    int qb = cu.kb;
-
-    // one batch step: cur holds the batch at qb; oth receives the next one.
-    // Returns true when the run is finished.
-    auto step = [&](Batch<VT, true, true, true> &cur, Batch<VT, true, true, true> &oth) -> bool {
-        const Entries<VT, true> Ec(ja, al, au, cu.kb, cu.k1);
-        {
-            // one load site for the next batch (this tile's, the next tile's
-            // first, or an empty range that reads zeros without memory
-            // traffic), so the compiler counts the loads in flight exactly
-            const bool in_tile = qb + 4 * B < cu.k1;
-            const int lb = in_tile ? cu.kb : (more ? nkb : 0);
-            const int le = in_tile ? cu.k1 : (more ? nk1 : 0);
-            const int lq = in_tile ? qb + 4 * B : lb;
-            oth.load(lq + 2 * tid, Entries<VT, true>(ja, al, au, lb, le));
-        }
-        const A *sx = bx(c);
-        S *sy = by(c);
-        const int r0 = cu.r0;
-        const PTile<E> &u = cu;
-        process_batch<VT, true, true>(
-            cur, qb + 2 * tid, Ec, brid(c), sx, [](int) { return true; },
-            [&](int j, A w) -> A {
-                const int idx = j >= r0 ? j - r0 : u.col_index(j);
-                atomic_add(&sy[idx], w);
-                return sx[idx];
-            },
-            [&](int r, A v) { atomic_add(&sy[r], v); });
-        qb += 4 * B;
-        if (qb < cu.k1) return false;
-        // tile done: every wave's copies for the next tile have landed (only
-        // the next tile's first batch may still be in flight)
-        wait_vm<BatchLoads<VT>::N>();
-        __syncthreads();
-        write_out(cu, c);
-        if (!more) return true;
-        ++t;
-        c ^= 1;
-        cu.read(P, t);
-        stage_finish(cu, c);
-        __syncthreads();
-        qb = cu.kb;
-        more = t + 1 < tb;
-        if (more) issue_next(t + 1, c ^ 1);
-        return false;
-    };
-    for (;;) {
-        if (step(bA, bB)) break;
-        if (step(bB, bA)) break;
-    }
-}
-
 // Merge pass: y_i += the partial slots covering row i, in ascending tile
 // order.  Merge block b (one workgroup, one row per thread) lists segments
 // [lo, hi) with partial index base + i; segments are taken four at a time so
@@ -1854,25 +1599,7 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
         const int emax = p->max_tile_entries, smax = p->max_span;
         if (single) {
             const size_t lds = (size_t)lds_private(smax, emax, p->max_intervals, sizeof(Acc));
-            if (p->o.persistent) {
-                const int buf = (int)align16((int64_t)lds_private_padded(p->max_span_padded, emax, sizeof(Acc)));
-                if (B != kPersistentBlock || p->max_intervals > kRegIntervals || 2 * (int64_t)buf > kLdsBudget)
-                    return CSRC_ERR_UNSUPPORTED;
-                auto kern = k_private_p<VT, YT>;
-                if (set_lds((const void *)kern, 2 * (size_t)buf)) return CSRC_ERR_HIP;
-                int grid = p->o.grid > 0 ? p->o.grid : p->persistent_grid.load(std::memory_order_relaxed);
-                if (grid <= 0) {
-                    int per_cu = 0;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kPersistentBlock,
-                                                                     2 * (size_t)buf) != hipSuccess ||
-                        per_cu < 1)
-                        per_cu = 1;
-                    grid = std::max(8, device_cus() * per_cu);
-                    p->persistent_grid.store(grid, std::memory_order_relaxed);
-                }
-                kern<<<grid, kPersistentBlock, 2 * (size_t)buf, s>>>(P, p->ntiles, n, A->ia, A->ja, ad, al, au, x, y,
-                                                                     p->max_span_padded, emax, buf);
-            } else if (p->o.atomic_merge) {
+            if (p->o.atomic_merge) {
                 k_fill_zero<YT><<<fill_grid(n), 256, 0, s>>>(y, n, 1, 1);
                 // numerically symmetric storage (au is al): one value load per entry
                 auto kern = private_kernel<VT, YT, kMergeAtomic>(p, al == au);
@@ -2087,7 +1814,7 @@ extern "C" int csrc_spmv_pair(const csrc_matrix *A, const csrc_plan *plan, const
     const int64_t xspan = (int64_t)A->n * xbytes(A->vdtype), yspan = (int64_t)A->n * ys;
     if (overlap(x, xspan, y, yspan) || overlap(x, xspan, yt, yspan) || overlap(y, yspan, yt, yspan))
         return CSRC_ERR_ALIAS;
-    const bool fused = plan->o.variant == CSRC_V_PRIVATE && plan->o.atomic_merge && !plan->o.persistent &&
+    const bool fused = plan->o.variant == CSRC_V_PRIVATE && plan->o.atomic_merge &&
                        lds_private_pair(plan->max_span, plan->max_tile_entries, plan->max_intervals,
                                         acc_bytes(A->vdtype)) <= kLdsBudget;
     if (!fused) {

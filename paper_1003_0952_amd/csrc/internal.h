@@ -46,12 +46,6 @@ inline int64_t lds_private_pair(int64_t smax, int64_t emax, int64_t ivmax, int a
 {
     return lds_xs(smax, acc) + align16(smax * kSumBytes) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
-// one buffer of the persistent PRIVATE kernel: x and sums of own rows and
-// window intervals, each padded to 16-byte chunks of x (spad values), row ids
-inline int64_t lds_private_padded(int64_t spad, int64_t emax, int acc)
-{
-    return lds_xs(spad, acc) + align16((emax + 4) * 2);
-}
 inline int64_t lds_owner(int64_t tmax, int64_t pmax, int64_t emax, int acc)
 {
     return align16((tmax + pmax) * acc) + align16(tmax * kSumBytes) + align16((emax + 4) * 2);
@@ -148,7 +142,6 @@ struct csrc_plan {
     int32_t max_tile_rows = 0;
     int32_t max_window = 0;     // PRIVATE: slots; OWNER: pulled rows
     int32_t max_span = 0;       // PRIVATE: largest rows + window slots of a tile
-    int32_t max_span_padded = 0;  // same with rows and intervals padded to 16 bytes
     int32_t max_intervals = 0;
     int32_t max_tile_entries = 0;   // stored lower entries of the largest tile
     int32_t max_pull_rows = 0;      // OWNER: rows of the largest pull chunk
@@ -156,7 +149,6 @@ struct csrc_plan {
     int64_t window_slots = 0;
     int64_t pulled_rows = 0;
     int64_t lds_bytes = 0;
-    mutable std::atomic<int> persistent_grid{0};  // resolved at the first persistent launch
     int32_t ncolors = 0;
     int32_t nmerge_blocks = 0;
     // host tables

@@ -15,23 +15,14 @@ from tests.helpers import small_cases, oracle_csrc, rel_inf
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_persistent", "private_atomic", "tile_color"]
+VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_atomic", "tile_color"]
 TOL = 1e-12
 
 
 def make_plan(C, A, variant, **kw):
-    """Plan of a variant name; private_persistent is PRIVATE with persistent
-    workgroups (block 512), private_atomic PRIVATE with the atomic merge."""
+    """Plan of a variant name; private_atomic is PRIVATE with the atomic merge."""
     if variant == "private_atomic":
         return C.Plan(A, "private", atomic_merge=1, **kw)
-    if variant == "private_persistent":
-        try:
-            return C.Plan(A, "private", persistent=1, **kw)
-        except C.CsrcError as e:
-            # refused only for tiles with more than 8 window intervals or
-            # staging buffers beyond the LDS (the host tests pin both rules)
-            assert e.status == -9
-            pytest.skip("persistent schedule refused for this matrix")
     return C.Plan(A, variant, **kw)
 
 
@@ -145,22 +136,6 @@ def test_repeated_products_identical(torch_cuda):
         y2 = C.spmv(A, plan, xt)
         torch.cuda.synchronize()
         assert rel_inf(y1.cpu().numpy(), y2.cpu().numpy()) <= 1e-15
-
-
-@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("tile_work,grid", [(300, 8), (700, 0), (1500, 24), (4000, 13)])
-def test_persistent_schedules(torch_cuda, case, tile_work, grid):
-    """Persistent PRIVATE over tile sizes and grids: several tiles per
-    workgroup, uneven tiles per XCD, grids that are not a multiple of 8."""
-    import paper_1003_0952_amd as C
-    name, a, x = CASES[case]
-    print(f"case {name} persistent tile_work {tile_work} grid {grid}", flush=True)
-    c = oracle_csrc(a)
-    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
-    for transpose in (False, True):
-        y, _ = run(torch_cuda, C, host, x, "private_persistent", transpose, tile_work=tile_work, grid=grid)
-        ref = (R.spmv_t if transpose else R.spmv)(c, x)
-        assert rel_inf(y, ref) <= TOL, (name, tile_work, grid, transpose, rel_inf(y, ref))
 
 
 @pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])

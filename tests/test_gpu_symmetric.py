@@ -14,7 +14,7 @@ from tests.test_gpu_spmv import make_plan
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_persistent", "private_atomic", "tile_color"]
+VARIANTS = ["plain", "atomic", "private", "color", "owner", "private_atomic", "tile_color"]
 CASES = small_cases("sym")
 
 

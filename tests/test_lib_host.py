@@ -198,54 +198,19 @@ def test_plan_options_rejected():
         HostPlan(h, "private", lanes=3)
     with pytest.raises(C.CsrcError):
         HostPlan(h, "private", block=100)
-    # atomic merge: PRIVATE only, not persistent, not compensated
-    for variant, kw in (("atomic", {}), ("owner", {}), ("private", {"persistent": 1}),
-                        ("private", {"compensated": 1}), ("private", {"atomic_merge": 2})):
+    # atomic merge: PRIVATE only, not compensated
+    for variant, kw in (("atomic", {}), ("owner", {}), ("private", {"compensated": 1}),
+                        ("private", {"atomic_merge": 2})):
         kw = dict(kw)
         kw.setdefault("atomic_merge", 1)
         with pytest.raises(C.CsrcError) as e:
             HostPlan(h, variant, **kw)
         assert e.value.status == -1, (variant, kw)
-    # persistent workgroups: PRIVATE only, 512 threads, grid 0 or >= 8
-    for variant, kw in (("atomic", {}), ("owner", {}), ("private", {"block": 256}),
-                        ("private", {"grid": 3}), ("private", {"persistent": 2})):
-        kw = dict(kw)
-        kw.setdefault("persistent", 1)
+    # the reserved fields must be zero
+    for kw in ({"persistent": 1}, {"grid": 16}):
         with pytest.raises(C.CsrcError) as e:
-            HostPlan(h, variant, **kw)
-        assert e.value.status == -1, (variant, kw)
-
-
-@pytest.mark.parametrize("make", MATS[:5])
-def test_persistent_plan_lds(make):
-    """A persistent plan is the same tiling; its LDS holds two buffers of x
-    and sums for own rows and window intervals, each padded to 16-byte
-    chunks, plus row ids.  Tiles with more than 8 intervals, or buffers
-    beyond the 160 KB of LDS, are refused."""
-    c, h = host_matrix(make())
-    a16 = lambda v: (v + 15) // 16 * 16
-    pad = lambda v: (v + 1) // 2 * 2          # FP64: two values per 16-byte chunk
-    for work in (700, 4000):
-        one = HostPlan(h, "private", tile_work=work)
-        tiles = one.export(0)
-        ivs = one.export(2).reshape(-1, 3)
-        nt = len(tiles) - 1
-        per_tile = np.bincount(ivs[:, 0], minlength=nt) if len(ivs) else np.zeros(nt, int)
-        spad = 0
-        for t in range(nt):
-            lens = ivs[ivs[:, 0] == t, 2]
-            spad = max(spad, pad(tiles[t + 1] - tiles[t]) + sum(pad(int(v)) for v in lens))
-        emax = int(max(c["ia"][tiles[t + 1]] - c["ia"][tiles[t]] for t in range(nt)))
-        lds = 2 * a16(a16(2 * spad * 8) + a16((emax + 4) * 2))
-        if per_tile.max() > 8 or lds > 160 * 1024:
-            with pytest.raises(C.CsrcError) as e:
-                HostPlan(h, "private", tile_work=work, persistent=1, grid=16)
-            assert e.value.status == -9
-            continue
-        two = HostPlan(h, "private", tile_work=work, persistent=1, grid=16)
-        assert np.array_equal(tiles, two.export(0))
-        assert np.array_equal(one.export(2), two.export(2))
-        assert two.info()["lds_bytes"] == lds
+            HostPlan(h, "private", **kw)
+        assert e.value.status == -1, kw
 
 
 def test_features_definition():

@@ -101,3 +101,28 @@ def test_csrc_select_matches_features_then_network(stored):
                            ctypes.byref(c))
     assert st == B.ERR_NO_MODEL and c.value == -5
     assert b"model" in B.lib.csrc_status_string(st)
+
+
+@pytest.mark.parametrize("hidden,classes", [(0, 10), (64, 65), (257, 10), (64, 0)])
+def test_csrc_select_rejects_bad_network_shape(hidden, classes):
+    """A network shape outside the library's limits is an argument error
+    (checked before the features, which colour the rows), and *candidate
+    stays untouched."""
+    import ctypes
+    from paper_1003_0952_amd import api as C, binding as B
+    from synth import workloads as W
+    a, _ = W.hex_mesh(12, "natural")
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    ia = np.ascontiguousarray(host["ia"], np.int32)
+    ja = np.ascontiguousarray(host["ja"], np.int32)
+    params = np.zeros(70000, np.float32)
+    mean = np.zeros(12, np.float32)
+    scale = np.ones(12, np.float32)
+    c = ctypes.c_int32(-5)
+    st = B.lib.csrc_select(host["n"], B.np_ptr(ia), B.np_ptr(ja), B.F64, hidden, classes, B.np_ptr(params),
+                           B.np_ptr(mean), B.np_ptr(scale), ctypes.byref(c))
+    assert st == B.ERR_ARG and c.value == -5
+    # the same call with a valid shape picks a class
+    st = B.lib.csrc_select(host["n"], B.np_ptr(ia), B.np_ptr(ja), B.F64, 64, 10, B.np_ptr(params),
+                           B.np_ptr(mean), B.np_ptr(scale), ctypes.byref(c))
+    assert st == B.OK and 0 <= c.value < 10
