@@ -91,30 +91,45 @@ class Copies:
         return one
 
 
-def time_plan(C, torch, cp, plan, steps, warmup):
-    """Mean ms per step (Ax then A^T x) over `steps` back-to-back steps after
-    `warmup`; HIP events only at the two ends of the timed region."""
+RUNS = 3   # timed runs per measurement; the median is reported (Sec. 4: median of 3 runs)
+
+
+def time_plan(C, torch, cp, plan, steps, warmup, runs=RUNS):
+    """Milliseconds per step (y = A x, then y = A^T x) of `runs` timed runs
+    of `steps` back-to-back steps each, after `warmup` untimed steps.  The
+    products rotate over the copies: step s runs A x on copy 2s and A^T x on
+    copy 2s + 1 (mod the number of copies), so no product re-reads the
+    arrays the one before it streamed.  HIP events at the two ends of each
+    run, on the stream the kernels are launched on, with a synchronize on
+    both sides."""
     ydt = plan.ytorch
     if not cp.y or cp.y[0].dtype != ydt:
         cp.outputs(torch, ydt)
     nc = len(cp.mats)
 
     def step(s):
-        c = s % nc
+        c = (2 * s) % nc
         C.csrc_spmv(cp.mats[c], plan, cp.x[c], cp.y[c])
+        c = (2 * s + 1) % nc
         C.csrc_spmv_t(cp.mats[c], plan, cp.x[c], cp.yt[c])
 
     for s in range(warmup):
         step(s)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for s in range(steps):
-        step(s)
-    t1.record()
-    torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps
+    out = []
+    s0 = warmup
+    stream = torch.cuda.current_stream()
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for s in range(steps):
+            step(s0 + s)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        s0 += steps
+        out.append(t0.elapsed_time(t1) / steps)
+    return out
 
 
 def time_products(C, torch, cp, plan, count, transpose):
@@ -161,40 +176,91 @@ def measured_traffic(workload, dtype, vname, vkw):
     return None
 
 
-def hbm_ceiling(torch, nbytes=2 * 2**30, reps=5):
-    """Measured ceiling: a plain device copy of nbytes, GB/s of bytes read plus
-    written (outside every timed region)."""
+def hbm_ceiling(torch, C, nbytes=2 * 2**30, reps=5):
+    """Measured ceilings (outside every timed region), each the median of 3
+    runs of `reps` passes over nbytes: a read stream (the library's
+    non-temporal 16-byte read kernel; every product here is an HBM read
+    stream with a small write side) and a copy (bytes read + written)."""
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    t1.record()
-    torch.cuda.synchronize()
-    gbs = 2 * nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
-    del src, dst
+    sink = torch.zeros(65536, dtype=torch.int32, device="cuda")
+
+    def rate(f, moved):
+        f()
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(reps):
+                f()
+            t1.record()
+            torch.cuda.synchronize()
+            runs.append(moved * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9)
+        return round(float(np.median(runs)), 1)
+
+    read = rate(lambda: C.csrc_stream_read(src, sink), nbytes)
+    copy = rate(lambda: C.csrc_stream_copy(src, dst), 2 * nbytes)
+    del src, dst, sink
     torch.cuda.empty_cache()
-    return {"copy_gbs": round(gbs, 1), "kind": f"device copy of {nbytes >> 20} MiB, bytes read + written"}
+    return {"read_gbs": read, "copy_gbs": copy,
+            "kind": f"hand-written read and copy kernels over {nbytes >> 20} MiB, median of 3 runs "
+                    f"(copy counts bytes read + written)"}
+
+
+def cpu_info():
+    """CPU model, logical CPUs of the host and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "allowed_cpus": len(os.sched_getaffinity(0))}
+
+
+def pinned(f):
+    """Run f() with this process pinned to one CPU (the first it may use),
+    then restore the affinity.  Returns (f(), cpu)."""
+    old = os.sched_getaffinity(0)
+    cpu = min(old)
+    os.sched_setaffinity(0, {cpu})
+    try:
+        return f(), cpu
+    finally:
+        os.sched_setaffinity(0, old)
 
 
 def cpu_baseline(host, x, budget_s=12.0):
-    """Oracle (plain sequential C, 1 thread) on the same matrix: y=Ax, y=A^T x."""
+    """The oracle (plain sequential C, one thread pinned to one CPU) on the
+    same matrix: steps of y = A x and y = A^T x.  Three runs of about
+    budget_s / 3 each; returns (steps per run, median seconds per step, cpu)."""
     from oracle import reference as R
     c = {"n": host["n"], "k": host["k"], "ia": host["ia"], "ja": host["ja"],
          "ad": host["ad"], "al": host["al"], "au": host["au"]}
-    R.spmv(c, x)  # load / warm
-    reps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
+
+    def run():
+        R.spmv(c, x)  # load / warm
+        t0 = time.perf_counter()
         R.spmv(c, x)
         R.spmv_t(c, x)
-        reps += 1
-    dt = (time.perf_counter() - t0) / reps
-    return reps, dt
+        one = time.perf_counter() - t0
+        reps = max(1, int(budget_s / 3 / max(one, 1e-6)))
+        per = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                R.spmv(c, x)
+                R.spmv_t(c, x)
+            per.append((time.perf_counter() - t0) / reps)
+        return reps, float(np.median(per))
+
+    (reps, dt), cpu = pinned(run)
+    return reps, dt, cpu
 
 
 def bench_rect(args):
@@ -234,23 +300,28 @@ def bench_rect(args):
     yts = [torch.empty(m, dtype=plans[0].ytorch, device="cuda") for _ in range(ncopy)]
 
     def step(s_):
-        c = s_ % ncopy
+        c = (2 * s_) % ncopy
         C.csrc_spmv_rect(mats[c], rps[c], plans[c], xs[c], ys[c])
+        c = (2 * s_ + 1) % ncopy
         C.csrc_spmv_rect_t(mats[c], rps[c], plans[c], xts[c], yts[c])
 
     for s_ in range(args.warmup):
         step(s_)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for s_ in range(args.steps):
-        step(s_)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
+    runs_ms = []
+    for run in range(RUNS):
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for s_ in range(args.steps):
+            step(args.warmup + run * args.steps + s_)
+        t1.record()
+        torch.cuda.synchronize()
+        runs_ms.append(t0.elapsed_time(t1) / args.steps)
+    ms = float(np.median(runs_ms))
     c0 = R.csr_to_csrc(n, srp, scol, sval)
-    step(0)
+    C.csrc_spmv_rect(mats[0], rps[0], plans[0], xs[0], ys[0])
+    C.csrc_spmv_rect_t(mats[0], rps[0], plans[0], xts[0], yts[0])
     torch.cuda.synchronize()
 
     def rel(a_, b_):
@@ -262,11 +333,12 @@ def bench_rect(args):
     nnz = 2 * k + n + kr
     out = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "timing": f"median of {RUNS} runs of {args.steps} steps each", "ms_per_step_runs": [round(v, 5) for v in runs_ms],
         "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": f"rect{side}_27pt_{args.dtype}", "n": n, "m": m, "nnz": nnz, "k": k, "kr": kr,
                    "variant": vname, **vkw, "copies": ncopy,
-                   "step": "y=(A_S+A_R)x then y=(A_S+A_R)^T x on the next rotated copy"},
+                   "step": "y=(A_S+A_R)x on copy 2s, then y=(A_S+A_R)^T x on copy 2s+1 (mod copies)"},
         "gflops": round(2 * (2 * (nnz - n) + n) / (ms * 1e-3) / 1e9, 1),
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "max_rel_err_vs_oracle": err,
@@ -322,20 +394,25 @@ def bench_batch(args):
         bp.bind(Xs, Ys)
         return bp, Ys, bp.graph(False), bp.graph(True)
 
-    def time_graphs(g, gt, steps, warmup):
+    def time_graphs(g, gt, steps, warmup, runs=RUNS):
+        """ms per step of `runs` timed runs of `steps` steps (forward graph
+        then transpose graph), events at the two ends of each run."""
         for _ in range(warmup):
             C.BatchPlan.launch_graph(g)
             C.BatchPlan.launch_graph(gt)
-        torch.cuda.synchronize()
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record()
-        for _ in range(steps):
-            C.BatchPlan.launch_graph(g)
-            C.BatchPlan.launch_graph(gt)
-        t1.record()
-        torch.cuda.synchronize()
-        return t0.elapsed_time(t1) / steps
+        out = []
+        for _ in range(runs):
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                C.BatchPlan.launch_graph(g)
+                C.BatchPlan.launch_graph(gt)
+            t1.record()
+            torch.cuda.synchronize()
+            out.append(t0.elapsed_time(t1) / steps)
+        return out
 
     # --- partition / tile shape: every batch candidate timed, fastest kept
     tuning = []
@@ -349,7 +426,7 @@ def bench_batch(args):
         except C.CsrcError as e:
             tuning.append({"candidate": kw, "error": str(e)})
             continue
-        ms = time_graphs(g, gt, args.tune_steps, 2)
+        ms = float(np.median(time_graphs(g, gt, args.tune_steps, 2)))
         tuning.append({"candidate": kw, "ms_per_step": round(ms, 4)})
         print(f"# tune {kw} {ms:.4f} ms/step", file=sys.stderr, flush=True)
         if best is None or ms < best[1]:
@@ -357,7 +434,8 @@ def bench_batch(args):
         del bp, Ys, g, gt
     kw = best[0]
     bp, Ys, g, gt = make(kw)
-    ms = time_graphs(g, gt, args.steps, args.warmup)
+    runs_ms = time_graphs(g, gt, args.steps, args.warmup)
+    ms = float(np.median(runs_ms))
 
     # parity spot check: the forward and transpose graphs on sampled members
     sample = sorted({0, 1, 64, 127, 128, 200, 254, 255, max(range(BATCH_COUNT), key=lambda i: mats[i].n)})
@@ -376,38 +454,41 @@ def bench_batch(args):
 
     cpu = None
     if not args.no_cpu:
-        # passes over the members until about 12 s of products (only the
-        # products are timed, not the oracle's own CSRC split)
-        dt = 0.0
-        done_b = 0
-        done_m = 0
-        split = {}
-        while dt <= 12.0:
-            for i in range(BATCH_COUNT):
-                a, X = members[i]
-                if i not in split:
-                    split[i] = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
-                c = split[i]
-                t0 = time.perf_counter()
-                for j in range(X.shape[1]):
-                    xj = np.ascontiguousarray(X[:, j])
-                    R.spmv(c, xj)
-                    R.spmv_t(c, xj)
-                dt += time.perf_counter() - t0
-                done_b += 2 * algorithmic_bytes(c["n"], c["k"], vb, xb, xb, X.shape[1])
-                done_m += 1
-                if dt > 12.0:
-                    break
-        del split
+        # passes over the members until about 12 s of products, pinned to one
+        # CPU (only the products are timed, not the oracle's own CSRC split)
+        def run_cpu():
+            dt = 0.0
+            done_b = 0
+            done_m = 0
+            split = {}
+            while dt <= 12.0:
+                for i in range(BATCH_COUNT):
+                    a, X = members[i]
+                    if i not in split:
+                        split[i] = R.csr_to_csrc(a.n, a.rowptr, a.col, a.val)
+                    c = split[i]
+                    t0 = time.perf_counter()
+                    for j in range(X.shape[1]):
+                        xj = np.ascontiguousarray(X[:, j])
+                        R.spmv(c, xj)
+                        R.spmv_t(c, xj)
+                    dt += time.perf_counter() - t0
+                    done_b += 2 * algorithmic_bytes(c["n"], c["k"], vb, xb, xb, X.shape[1])
+                    done_m += 1
+                    if dt > 12.0:
+                        break
+            return dt, done_b, done_m
+        (dt, done_b, done_m), core = pinned(run_cpu)
         cpu = {"value": round(done_b / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"{done_m} members in batch order ({done_m / BATCH_COUNT:.2f} passes over the batch), "
                          f"every right-hand side, y=Ax and y=A^T x, "
-                         f"plain sequential C oracle (FP64 values), {dt:.1f} s"}
+                         f"plain sequential C oracle (FP64 values) pinned to CPU {core}, {dt:.1f} s",
+               "pinned_cpu": core, **cpu_info()}
 
     gbs = 2 * B1 / (ms * 1e-3) / 1e9
     ach = gbs
-    ceiling = hbm_ceiling(torch)
-    ceiling["value_frac_of_ceiling"] = round(gbs / ceiling["copy_gbs"], 4)
+    ceiling = hbm_ceiling(torch, C)
+    ceiling["value_frac_of_read_ceiling"] = round(gbs / ceiling["read_gbs"], 4)
     out = {
         "metric": METRIC,
         "value": round(gbs, 1),
@@ -416,6 +497,8 @@ def bench_batch(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 5),
+        "timing": f"median of {RUNS} runs of {args.steps} steps each",
+        "ms_per_step_runs": [round(v, 5) for v in runs_ms],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -512,7 +595,7 @@ def main():
             except C.CsrcError as e:
                 tuning.append({"candidate": T.candidate_name(i), "error": str(e)})
                 continue
-            ms = time_plan(C, torch, cp, plan, args.tune_steps, 3)
+            ms = float(np.median(time_plan(C, torch, cp, plan, args.tune_steps, 3)))
             tms[i] = ms
             tuning.append({"candidate": T.candidate_name(i), "ms_per_step": round(ms, 4)})
             print(f"# tune {T.candidate_name(i)} {ms:.4f} ms/step", file=sys.stderr, flush=True)
@@ -546,9 +629,11 @@ def main():
     plan = C.Plan(cp.mats[0], vname, **vkw)
     info = plan.info()
 
-    # --- timed region: back-to-back steps, events at its two ends; a product
-    # (all launches of one y = A x or y = A^T x) takes half a step
-    ms = time_plan(C, torch, cp, plan, args.steps, args.warmup)
+    # --- timed regions: three runs of back-to-back steps, events at the two
+    # ends of each; the median run is the headline.  A product (all launches
+    # of one y = A x or y = A^T x) takes half a step.
+    runs_ms = time_plan(C, torch, cp, plan, args.steps, args.warmup)
+    ms = float(np.median(runs_ms))
     per_prod_ms = ms / 2
     # the two product kinds apart, in passes of their own
     fwd = time_products(C, torch, cp, plan, min(args.steps, 50), False)
@@ -562,7 +647,7 @@ def main():
     plain = None
     if not args.no_plain:
         pplan = C.Plan(cp.mats[0], "plain")
-        pms = time_plan(C, torch, cp, pplan, max(10, args.steps // 4), 3)
+        pms = float(np.median(time_plan(C, torch, cp, pplan, max(10, args.steps // 4), 3)))
         plain = {"ms_per_step": round(pms, 4), "value": round(2 * B1 / (pms * 1e-3) / 1e9, 1),
                  "gflops": round(2 * flops(n, k) / (pms * 1e-3) / 1e9, 1),
                  "pct_hbm_peak": round(100 * 2 * B1 / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2)}
@@ -612,15 +697,15 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        reps, dt = cpu_baseline(c0, x)
+        reps, dt, core = cpu_baseline(c0, x)
         cpu = {"value": round(2 * B1 / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"full {args.workload} matrix, {reps} steps (y=Ax and y=A^T x each), "
-                         f"plain sequential C oracle, {dt*1e3:.1f} ms/step",
-               "gflops": round(2 * flops(n, k) / dt / 1e9, 3)}
+               "sample": f"full {args.workload} matrix, median of 3 runs of {reps} steps (y=Ax and y=A^T x "
+                         f"each), plain sequential C oracle pinned to CPU {core}, {dt*1e3:.1f} ms/step",
+               "gflops": round(2 * flops(n, k) / dt / 1e9, 3), "pinned_cpu": core, **cpu_info()}
 
     ach = B1 / (per_prod_ms * 1e-3) / 1e9
-    ceiling = hbm_ceiling(torch)
-    ceiling["value_frac_of_ceiling"] = round(gbs / ceiling["copy_gbs"], 4)
+    ceiling = hbm_ceiling(torch, C)
+    ceiling["value_frac_of_read_ceiling"] = round(gbs / ceiling["read_gbs"], 4)
     if vname == "private":
         launches = ("one product = k_fill_zero + k_private (atomic merge)" if vkw.get("atomic_merge")
                     else "one product = k_private + k_merge")
@@ -635,6 +720,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 5),
+        "timing": f"median of {RUNS} runs of {args.steps} steps each",
+        "ms_per_step_runs": [round(v, 5) for v in runs_ms],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -643,7 +730,7 @@ def main():
         "config": {"workload": f"{args.workload}_27pt_{args.dtype}" if args.workload.startswith("hex")
                    else args.workload, "n": n, "nnz": 2 * k + n, "k": k, "variant": vname, **vkw,
                    "lanes": info["lanes"], "ntiles": info["ntiles"], "copies": ncopy,
-                   "step": "y=Ax then y=A^T x on the next rotated copy"},
+                   "step": "y=Ax on copy 2s, then y=A^T x on copy 2s+1 (mod copies)"},
         "gflops": round(gfl, 1),
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "us_per_product": {"Ax": round(fwd * 1e3, 2), "ATx": round(bwd * 1e3, 2)},
