@@ -11,5 +11,6 @@ from .api import (  # noqa: F401
     csrc_spmv, csrc_spmv_t, csrc_spmv_pair, csrc_spmm, csrc_spmm_t, spmv,
     RectPart, csrc_rect_split, csrc_spmv_rect, csrc_spmv_rect_t,
     BatchPlan, csrc_spmv_batched, csrc_spmv_t_batched,
+    csrc_stream_read, csrc_stream_copy,
 )
 from .binding import CsrcError, VARIANTS, VARIANT_NAMES, DTYPES  # noqa: F401

@@ -63,3 +63,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_package_exports_what_the_benchmark_and_smoke_use():
+    """Every ``C.<name>`` that bench.py and the smoke entry call is exported
+    by the package (a missing export only shows on the GPU otherwise)."""
+    import re
+    import paper_1003_0952_amd as C
+    for f in ("bench.py", "__graft_entry__.py"):
+        src = open(os.path.join(ROOT, f)).read()
+        for name in sorted(set(re.findall(r"\bC\.([A-Za-z_][A-Za-z0-9_]*)", src))):
+            assert hasattr(C, name), f"{f} uses C.{name}, which the package does not export"

@@ -128,3 +128,47 @@ def test_compensated_merge_recovers_accuracy(transpose):
           f"compensated max {errs[True][0]:.3e} rms {errs[True][1]:.3e}")
     assert errs[True][0] * 4 <= errs[False][0]
     assert errs[True][1] * 4 <= errs[False][1]
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_atomic_merge_fp64_output_recovers_accuracy(transpose):
+    """The atomic merge adds every tile's window sums straight into y with
+    hardware atomics, so it has no TwoSum form; its accurate form is an FP64
+    y (FP32 or BF16 storage, ydtype f64): the merge then runs in FP64.  On
+    the case of the compensated test (384 FP32 window partials per row) the
+    FP64-output error against the FP64 oracle on the stored values is at
+    least four times below the FP32-output error, in the largest row and in
+    the root mean square, and both stay within the accumulation bound."""
+    import torch
+    import paper_1003_0952_amd as C
+    from synth import patterns as P
+    from synth.values import fill_values, vector
+    a = P.banded(4096, 384, 1.0, 11)
+    fill_values(a, 12)
+    x = vector(a, 13)
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    ov = {s: R.dequantize(c[s], "f32") for s in ("ad", "al", "au")}
+    xf = R.to_f32(x).astype(np.float64)
+    f = R.spmv_t if transpose else R.spmv
+    ref = f(c, xf, **ov)
+    scale = R.abs_product(c, xf, transpose, **ov)
+    bound = R.accumulation_bound(c, xf, 2.0**-24, transpose, **ov) + 2.0**-24 * np.abs(ref)
+    A = C.Matrix(host, "f32")
+    xt = torch.from_numpy(x).to("cuda", torch.float32)
+    errs = {}
+    for ydt in ("f32", "f64"):
+        plan = C.Plan(A, "private", ydtype=ydt, tile_work=1, atomic_merge=1)
+        assert plan.info()["ntiles"] == a.n
+        y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+        (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
+        torch.cuda.synchronize()
+        yh = y.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(yh - ref) <= bound), ydt
+        e = _rel_to_scale(yh, ref, scale)
+        errs[ydt] = (float(e.max()), float(np.sqrt(np.mean(e * e))))
+    print(f"atomic merge of 384 partials per row, transpose={transpose}: "
+          f"FP32 y max {errs['f32'][0]:.3e} rms {errs['f32'][1]:.3e}; "
+          f"FP64 y max {errs['f64'][0]:.3e} rms {errs['f64'][1]:.3e}")
+    assert errs["f64"][0] * 4 <= errs["f32"][0]
+    assert errs["f64"][1] * 4 <= errs["f32"][1]

@@ -66,5 +66,10 @@ def test_rect_rejects_mismatched_part():
     plan = C.Plan(A, "private")
     xt = torch.from_numpy(x).cuda()
     y = torch.empty(n, dtype=torch.float64, device="cuda")
-    with pytest.raises(C.CsrcError):
+    with pytest.raises(ValueError):         # the binding's check
         C.csrc_spmv_rect(A, Rf, plan, xt, y)
+    import ctypes
+    from paper_1003_0952_amd import binding as B
+    st = B.lib.csrc_spmv_rect(ctypes.byref(A.desc), ctypes.byref(Rf.desc), plan.handle, B.t_ptr(xt),
+                              B.t_ptr(y), B.t_ptr(plan.workspace), plan.ws_bytes, B.stream_ptr())
+    assert st == B.ERR_ARG                  # and the library's own
