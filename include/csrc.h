@@ -305,6 +305,27 @@ int csrc_plan_export(const csrc_plan *plan, int32_t what, int32_t *dst,
 int csrc_spmv(const csrc_matrix *A, const csrc_plan *plan, const void *x,
               void *y, void *workspace, int64_t ws_bytes, void *stream);
 
+/*
+ * csrc_spmv_noalloc -- csrc_spmv without a workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The plan's tables and partial
+ * buffer are placed in a static device array of the library,
+ * CSRC_NOALLOC_MAX_BYTES per device, held from the library's load until the
+ * process ends; each call copies the plan's tables into it (asynchronously
+ * on stream: the plan must outlive the product) and then runs the kernels of
+ * csrc_spmv.  No device or host memory is allocated.  Every call on a device
+ * shares that device's array, so calls that overlap on one device (other
+ * streams, other threads) race; serialise them.  Results equal csrc_spmv's
+ * with the same plan.
+ * Errors: as csrc_spmv; WORKSPACE when csrc_plan_workspace_bytes(plan)
+ * exceeds CSRC_NOALLOC_MAX_BYTES (the 27-point 100^3 matrix needs 16 MiB
+ * with PRIVATE 8192-work tiles and a merge pass, under 1 MiB with the atomic
+ * merge).
+ */
+#define CSRC_NOALLOC_MAX_BYTES (32 * 1024 * 1024)
+int csrc_spmv_noalloc(const csrc_matrix *A, const csrc_plan *plan, const void *x,
+                      void *y, void *stream);
+
 /* csrc_spmv_t -- y <- A^T x: the same kernels with al and au exchanged (Sec. 5). */
 int csrc_spmv_t(const csrc_matrix *A, const csrc_plan *plan, const void *x,
                 void *y, void *workspace, int64_t ws_bytes, void *stream);

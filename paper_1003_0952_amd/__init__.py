@@ -8,7 +8,7 @@ hand-written HIP kernels behind the C ABI of ``include/csrc.h``
 
 from .api import (  # noqa: F401
     Matrix, Plan, csrc_count, csrc_from_csr, csrc_quantize, csrc_color, csrc_features,
-    csrc_spmv, csrc_spmv_t, csrc_spmv_pair, csrc_spmm, csrc_spmm_t, spmv,
+    csrc_spmv, csrc_spmv_t, csrc_spmv_noalloc, csrc_spmv_pair, csrc_spmm, csrc_spmm_t, spmv,
     RectPart, csrc_rect_split, csrc_spmv_rect, csrc_spmv_rect_t,
     BatchPlan, csrc_spmv_batched, csrc_spmv_t_batched,
     csrc_stream_read, csrc_stream_copy,

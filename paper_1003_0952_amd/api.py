@@ -301,6 +301,19 @@ def csrc_spmv_t(A, plan, x, y, stream=None):
     return y
 
 
+def csrc_spmv_noalloc(A, plan, x, y, stream=None):
+    """y <- A x like csrc_spmv, with the plan's tables and partials in the
+    library's static device array instead of the plan's workspace (no
+    allocation in the call).  Asynchronous on the stream; calls that
+    overlap on one device race."""
+    _check_plan(A, plan)
+    _vector(x, A.n, _xdtype(A.vdtype), A.device, "x")
+    _vector(y, A.n, plan.ytorch, A.device, "y")
+    check(B.lib.csrc_spmv_noalloc(ctypes.byref(A.desc), plan.handle, t_ptr(x), t_ptr(y), stream_ptr(stream)),
+          "csrc_spmv_noalloc")
+    return y
+
+
 def csrc_spmv_pair(A, plan, x, y, yt, stream=None):
     """y <- A x and yt <- A^T x (one pass over the entries with a PRIVATE
     atomic-merge plan).  Asynchronous on the stream."""

@@ -59,6 +59,7 @@ PAD_PATTERN = 1
 COLOR_WRITE_SET = 0
 COLOR_DISTANCE2 = 1
 NFEATURES = 12
+NOALLOC_MAX_BYTES = 32 * 1024 * 1024   # CSRC_NOALLOC_MAX_BYTES
 
 
 class CsrcError(RuntimeError):
@@ -130,6 +131,7 @@ _sig("csrc_plan_get_info", ctypes.c_int, [P, P])
 _sig("csrc_plan_export", ctypes.c_int, [P, I32, P, I64, P])
 _sig("csrc_spmv", ctypes.c_int, [P, P, P, P, P, I64, P])
 _sig("csrc_spmv_t", ctypes.c_int, [P, P, P, P, P, I64, P])
+_sig("csrc_spmv_noalloc", ctypes.c_int, [P, P, P, P, P])
 _sig("csrc_spmv_pair", ctypes.c_int, [P, P, P, P, P, P, I64, P])
 _sig("csrc_spmm", ctypes.c_int, [P, P, I32, P, I64, P, I64, P, I64, P])
 _sig("csrc_spmm_t", ctypes.c_int, [P, P, I32, P, I64, P, I64, P, I64, P])

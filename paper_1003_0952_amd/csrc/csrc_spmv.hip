@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "device_common.h"
@@ -1773,6 +1774,72 @@ extern "C" int csrc_spmm_t(const csrc_matrix *A, const csrc_plan *plan, int32_t 
                            void *Y, int64_t ldy, void *workspace, int64_t ws_bytes, void *stream)
 {
     return csrc::product(A, plan, r, X, ldx, Y, ldy, workspace, ws_bytes, stream, true);
+}
+
+// ------------------------------------------------ product without a workspace
+//
+// For callers that cannot allocate device memory, csrc_spmv_noalloc places
+// the plan's tables and its partial buffer in `scratch`, a static device
+// array of this source file that each device holds once, for the life of the
+// process.  Its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current; host code uses only that address.
+// Nothing in it needs to start at zero: the plan tables are copied in by
+// every call, and every partial slot a merge reads is written first by its
+// tile in the same call.  Calls that overlap on one device share the array
+// and race.
+
+namespace csrc {
+
+static __device__ __align__(256) unsigned char scratch[CSRC_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+static int scratch_address(void **out)
+{
+    int dev = 0;
+    int st = hip_status(hipGetDevice(&dev));
+    if (st) return st;
+    if (dev < 0 || dev >= kMaxDevices) return CSRC_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        st = hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (st) return st;
+        if (!p) return CSRC_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CSRC_OK;
+}
+
+}  // namespace csrc
+
+extern "C" int csrc_spmv_noalloc(const csrc_matrix *A, const csrc_plan *plan, const void *x, void *y,
+                                 void *stream)
+{
+    using namespace csrc;
+    if (!A || !plan) return CSRC_ERR_ARG;
+    if (plan->ws_bytes > (int64_t)CSRC_NOALLOC_MAX_BYTES) return CSRC_ERR_WORKSPACE;
+    void *ws = nullptr;
+    int st = CSRC_OK;
+    if (plan->ws_bytes > 0) {
+        st = scratch_address(&ws);
+        if (st) return st;
+    }
+    st = check_call(A, plan, ws, plan->ws_bytes);
+    if (st) return st;
+    if (A->n == 0) return CSRC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->blob_bytes > 0) {
+        // the plan's host image outlives the call (the caller keeps the plan
+        // until the product is done), so the copy is left asynchronous
+        st = hip_status(hipMemcpyAsync(ws, plan->blob.data(), (size_t)plan->blob_bytes, hipMemcpyHostToDevice, s));
+        if (st) return st;
+    }
+    return product(A, plan, 1, x, 1, y, 1, ws, plan->ws_bytes, stream, false);
 }
 
 namespace csrc {
