@@ -101,10 +101,6 @@ extern "C" int csrc_batch_plan_destroy(csrc_batch_plan *b)
 
 extern "C" int64_t csrc_batch_workspace_bytes(const csrc_batch_plan *b) { return b ? b->ws_bytes : -1; }
 
-namespace csrc {
-PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials);
-}
-
 extern "C" int csrc_batch_bind(const csrc_batch_plan *b, const csrc_matrix *A, const void *const *X,
                                const int64_t *ldx, void *const *Y, const int64_t *ldy, void *workspace,
                                int64_t ws_bytes, void *stream)

@@ -1,6 +1,6 @@
 // Selector network on the GPU: a 12-H-H-K perceptron (ReLU, softmax
-// cross-entropy) with forward, backward and Adam kernels, and a host-side
-// forward pass for inference.  All FP32.  Parameters: W1[H,12] b1[H]
+// cross-entropy) with forward, backward and Adam kernels (the host-side
+// forward pass for inference is in csrc_mlp_host.cpp).  All FP32.  Parameters: W1[H,12] b1[H]
 // W2[H,H] b2[H] W3[K,H] b3[K], row-major W[out, in].
 #include <hip/hip_runtime.h>
 
@@ -13,23 +13,6 @@
 namespace csrc {
 
 constexpr int kNF = CSRC_NFEATURES;
-
-struct MlpLayout {
-    int64_t W1, b1, W2, b2, W3, b3, total;
-};
-
-__host__ __device__ inline MlpLayout mlp_layout(int H, int K)
-{
-    MlpLayout L;
-    L.W1 = 0;
-    L.b1 = L.W1 + (int64_t)H * kNF;
-    L.W2 = L.b1 + H;
-    L.b2 = L.W2 + (int64_t)H * H;
-    L.W3 = L.b2 + H;
-    L.b3 = L.W3 + (int64_t)K * H;
-    L.total = L.b3 + K;
-    return L;
-}
 
 // One workgroup per sample; blockDim >= max(H, K).
 __global__ void k_mlp_forward(int H, int K, int B, const float *__restrict__ p, const float *__restrict__ X,
@@ -174,8 +157,6 @@ __global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict
     }
 }
 
-static bool mlp_shape_ok(int H, int K, int B) { return H >= 1 && H <= 256 && K >= 1 && K <= 64 && B >= 0; }
-
 static int mlp_block(int H, int K)
 {
     int t = H > K ? H : K;
@@ -184,12 +165,6 @@ static int mlp_block(int H, int K)
 }
 
 }  // namespace csrc
-
-extern "C" int64_t csrc_mlp_param_count(int32_t hidden, int32_t classes)
-{
-    if (!csrc::mlp_shape_ok(hidden, classes, 0)) return -1;
-    return csrc::mlp_layout(hidden, classes).total;
-}
 
 extern "C" int csrc_mlp_forward(int32_t H, int32_t K, int32_t B, const float *params, const float *feats, float *act,
                                 float *logits, float *probs, void *stream)
@@ -232,34 +207,4 @@ extern "C" int csrc_mlp_adam(int64_t count, float *params, const float *grads, f
     k_adam<<<grid, 256, 0, static_cast<hipStream_t>(stream)>>>(count, params, grads, m, v, lr, beta1, beta2, eps, c1,
                                                                c2);
     return hip_status(hipGetLastError());
-}
-
-extern "C" int csrc_mlp_predict_host(int32_t H, int32_t K, const float *p, const float *mean, const float *scale,
-                                     const float *features, int32_t *cls)
-{
-    using namespace csrc;
-    if (!mlp_shape_ok(H, K, 1) || !p || !mean || !scale || !features || !cls) return CSRC_ERR_ARG;
-    const MlpLayout L = mlp_layout(H, K);
-    float f[kNF];
-    for (int i = 0; i < kNF; ++i) f[i] = (features[i] - mean[i]) / (scale[i] != 0.f ? scale[i] : 1.f);
-    std::vector<float> h1(H), h2(H);
-    for (int h = 0; h < H; ++h) {
-        float s = p[L.b1 + h];
-        for (int i = 0; i < kNF; ++i) s += p[L.W1 + (int64_t)h * kNF + i] * f[i];
-        h1[h] = s > 0.f ? s : 0.f;
-    }
-    for (int h = 0; h < H; ++h) {
-        float s = p[L.b2 + h];
-        for (int i = 0; i < H; ++i) s += p[L.W2 + (int64_t)h * H + i] * h1[i];
-        h2[h] = s > 0.f ? s : 0.f;
-    }
-    int best = 0;
-    float bz = 0.f;
-    for (int k = 0; k < K; ++k) {
-        float s = p[L.b3 + k];
-        for (int i = 0; i < H; ++i) s += p[L.W3 + (int64_t)k * H + i] * h2[i];
-        if (k == 0 || s > bz) { bz = s; best = k; }
-    }
-    *cls = best;
-    return CSRC_OK;
 }

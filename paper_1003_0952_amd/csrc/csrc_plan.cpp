@@ -465,3 +465,29 @@ extern "C" int csrc_plan_export(const csrc_plan *p, int32_t what, int32_t *dst, 
     if (!v.empty()) std::memcpy(dst, v.data(), v.size() * 4);
     return CSRC_OK;
 }
+
+namespace csrc {
+
+// Device pointers of a plan's tables placed at base (its uploaded image) and
+// of its partial buffer.
+PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials)
+{
+    auto at = [&](const Table &t) -> const void * { return base ? base + t.offset : nullptr; };
+    PlanDev d;
+    d.tiles = (const int32_t *)at(p->t_tiles);
+    d.tile_k = (const int32_t *)at(p->t_tile_k);
+    d.iv_ptr = (const int32_t *)at(p->t_iv_ptr);
+    d.iv_row = (const int32_t *)at(p->t_iv_row);
+    d.iv_len = (const int32_t *)at(p->t_iv_len);
+    d.iv_slot = (const int32_t *)at(p->t_iv_slot);
+    d.iv_goff = (const int64_t *)at(p->t_iv_goff);
+    d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
+    d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
+    d.trec = (const TileRec *)at(p->t_trec);
+    d.crow = (const int32_t *)at(p->t_crow);
+    d.cptr = nullptr;
+    d.partials = partials;
+    return d;
+}
+
+}  // namespace csrc

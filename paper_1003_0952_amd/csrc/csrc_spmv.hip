@@ -1501,45 +1501,11 @@ __global__ __launch_bounds__(512) void k_color(const int32_t *__restrict__ crow,
 
 // --------------------------------------------------------------- dispatch
 
-PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials)
-{
-    auto at = [&](const Table &t) -> const void * { return base ? base + t.offset : nullptr; };
-    PlanDev d;
-    d.tiles = (const int32_t *)at(p->t_tiles);
-    d.tile_k = (const int32_t *)at(p->t_tile_k);
-    d.iv_ptr = (const int32_t *)at(p->t_iv_ptr);
-    d.iv_row = (const int32_t *)at(p->t_iv_row);
-    d.iv_len = (const int32_t *)at(p->t_iv_len);
-    d.iv_slot = (const int32_t *)at(p->t_iv_slot);
-    d.iv_goff = (const int64_t *)at(p->t_iv_goff);
-    d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
-    d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
-    d.trec = (const TileRec *)at(p->t_trec);
-    d.crow = (const int32_t *)at(p->t_crow);
-    d.cptr = nullptr;
-    d.partials = partials;
-    return d;
-}
-
+// Device view of a plan whose tables sit at the workspace ws (partials after them).
 static PlanDev plan_dev(const csrc_plan *p, void *ws)
 {
     char *b = static_cast<char *>(ws);
-    auto at = [&](const Table &t) -> const void * { return b ? b + t.offset : nullptr; };
-    PlanDev d;
-    d.tiles = (const int32_t *)at(p->t_tiles);
-    d.tile_k = (const int32_t *)at(p->t_tile_k);
-    d.iv_ptr = (const int32_t *)at(p->t_iv_ptr);
-    d.iv_row = (const int32_t *)at(p->t_iv_row);
-    d.iv_len = (const int32_t *)at(p->t_iv_len);
-    d.iv_slot = (const int32_t *)at(p->t_iv_slot);
-    d.iv_goff = (const int64_t *)at(p->t_iv_goff);
-    d.mb_ptr = (const int32_t *)at(p->t_mb_ptr);
-    d.mb_seg = (const MergeSeg *)at(p->t_mb_seg);
-    d.trec = (const TileRec *)at(p->t_trec);
-    d.crow = (const int32_t *)at(p->t_crow);
-    d.cptr = nullptr;
-    d.partials = b ? b + p->t_partials.offset : nullptr;
-    return d;
+    return plan_dev_at(p, b, b ? b + p->t_partials.offset : nullptr);
 }
 
 static int device_cus();

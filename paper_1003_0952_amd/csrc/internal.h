@@ -131,6 +131,27 @@ struct MatDev {
     int32_t r;
 };
 
+// Parameter layout of the selector network (12-H-H-K perceptron): offsets
+// of W1[H,12] b1[H] W2[H,H] b2[H] W3[K,H] b3[K] in one float array.
+// constexpr, so host and device code share it.
+constexpr int kMlpFeatures = CSRC_NFEATURES;
+struct MlpLayout {
+    int64_t W1, b1, W2, b2, W3, b3, total;
+};
+constexpr MlpLayout mlp_layout(int H, int K)
+{
+    MlpLayout L{};
+    L.W1 = 0;
+    L.b1 = L.W1 + (int64_t)H * kMlpFeatures;
+    L.W2 = L.b1 + H;
+    L.b2 = L.W2 + (int64_t)H * H;
+    L.W3 = L.b2 + H;
+    L.b3 = L.W3 + (int64_t)K * H;
+    L.total = L.b3 + K;
+    return L;
+}
+constexpr bool mlp_shape_ok(int H, int K, int B) { return H >= 1 && H <= 256 && K >= 1 && K <= 64 && B >= 0; }
+
 }  // namespace csrc
 
 struct csrc_plan {
@@ -172,6 +193,8 @@ int hip_status(int hip_error);
 // host helpers implemented in csrc_host.cpp
 int color_rows(int32_t n, const int32_t *ia, const int32_t *ja, int32_t criterion,
                int32_t *color, int32_t *ncolors);
+// device view of a plan's tables uploaded at base (csrc_plan.cpp)
+PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials);
 }
 
 // A batch of independent products: one PRIVATE plan per matrix, their tables
