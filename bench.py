@@ -419,7 +419,8 @@ def bench_batch(args):
     best = None
     cands = T.BATCH_CANDIDATES
     if args.tile_work or args.block:
-        cands = [{"tile_work": args.tile_work, "block": args.block}]
+        cands = [{"variant": "private" if args.variant == "private" else "owner",
+                  "tile_work": args.tile_work, "block": args.block}]
     for kw in cands:
         try:
             bp, Ys, g, gt = make(kw)
@@ -515,7 +516,8 @@ def bench_batch(args):
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "one product = k_batch_tiles + k_batch_merge (one graph launch)",
+                     "kernel": ("one product = k_batch_pull (one graph launch)" if kw.get("variant", "owner") == "owner"
+                                else "one product = k_batch_tiles + k_batch_merge (one graph launch)"),
                      "bytes_per_launch": B1, "duration_us": round(ms / 2 * 1e3, 2)},
         "cpu_baseline": cpu,
     }

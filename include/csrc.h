@@ -392,14 +392,25 @@ typedef struct csrc_batch_opts {
     int32_t block;       /* threads per workgroup; 0 = default               */
     int32_t grid;        /* persistent workgroups; 0 = one per CU x occupancy */
     int32_t ydtype;      /* as csrc_plan_opts.ydtype                          */
+    int32_t variant;     /* 0 or CSRC_V_OWNER: owner tiles, one launch;
+                            CSRC_V_PRIVATE: local-buffer tiles + merge launch */
 } csrc_batch_opts;
 
 /*
  * csrc_batch_plan_create -- plan for nmat independent products in one
  * persistent launch.  Per matrix m: n[m], host structure ia[m], ja[m] and
- * its number of right-hand sides r[m] (1..32).  The plan cuts every matrix
- * into PRIVATE tiles (local buffers of Sec. 3.1 in LDS) and orders the work
- * list by decreasing cost.
+ * its number of right-hand sides r[m] (1..32).
+ *   OWNER (default): every matrix is cut into owner tiles; a lane group of
+ *     G >= r lanes (a power of two, 4..32) holds a row's r columns, gathers
+ *     the tile's rows in registers and pulls the scatters into the tile from
+ *     the rows that make them (LDS sums), then stores Y once.  The work list
+ *     is in matrix order, cut into eight ranges of equal cost, one per XCD.
+ *     One kernel launch, no partial buffer.
+ *   PRIVATE: local buffers of Sec. 3.1 in LDS, C columns at a time; window
+ *     sums go to a partial buffer that a second launch merges; work list by
+ *     decreasing cost.
+ * Errors: ARG (bad r, n or variant), UNSUPPORTED (a tile's LDS exceeds the
+ * budget), NOMEM, TOO_LARGE.
  */
 int csrc_batch_plan_create(int32_t nmat, const int32_t *n,
                            const int32_t *const *ia, const int32_t *const *ja,
@@ -440,7 +451,8 @@ typedef struct csrc_graph csrc_graph;   /* opaque: an instantiated HIP graph */
 
 /*
  * csrc_batch_graph_create -- build (not capture) a HIP graph whose kernel
- * nodes are the launches of csrc_batch_run with these arguments, in order;
+ * nodes are the launches of csrc_batch_run with these arguments, in order
+ * (one node for OWNER plans, two for PRIVATE);
  * csrc_graph_launch replays it on a stream.  The workspace must stay bound.
  */
 int csrc_batch_graph_create(const csrc_batch_plan *plan, int32_t transpose,

@@ -391,7 +391,7 @@ class BatchPlan:
     right-hand sides (1..32).  The workspace lives as long as the plan.
     """
 
-    def __init__(self, mats, rs, tile_work=0, block=0, grid=0, ydtype="f32"):
+    def __init__(self, mats, rs, tile_work=0, block=0, grid=0, ydtype="f32", variant="owner"):
         import torch
         self.mats = list(mats)
         self.rs = [int(r) for r in rs]
@@ -403,7 +403,10 @@ class BatchPlan:
         ia_p = (ctypes.c_void_p * max(m, 1))(*[np_ptr(x).value for x in self._ia])
         ja_p = (ctypes.c_void_p * max(m, 1))(*[np_ptr(x).value for x in self._ja])
         r = np.array(self.rs, dtype=np.int32)
-        opts = B.BatchOpts(int(tile_work), int(block), int(grid), _dt(ydtype))
+        if variant not in ("owner", "private"):
+            raise ValueError("batch variant is 'owner' or 'private'")
+        opts = B.BatchOpts(int(tile_work), int(block), int(grid), _dt(ydtype), B.VARIANTS[variant])
+        self.variant = variant
         h = ctypes.c_void_p(0)
         check(B.lib.csrc_batch_plan_create(m, np_ptr(n), ia_p, ja_p, np_ptr(r), vd, ctypes.byref(opts),
                                            ctypes.byref(h)), "csrc_batch_plan_create")

@@ -101,7 +101,7 @@ class PlanInfo(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("tile_work", I32), ("block", I32), ("grid", I32), ("ydtype", I32)]
+    _fields_ = [("tile_work", I32), ("block", I32), ("grid", I32), ("ydtype", I32), ("variant", I32)]
 
 
 def _sig(name, res, args):

@@ -1,5 +1,6 @@
-// Host-side setup of batched products: a PRIVATE plan per matrix, their
-// tables concatenated, and the work lists of the persistent launch.
+// Host-side setup of batched products: an OWNER (or PRIVATE) plan per
+// matrix, their tables concatenated, and the work lists of the persistent
+// launch.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -8,6 +9,76 @@
 #include <vector>
 
 #include "internal.h"
+
+namespace {
+
+void put_ints(csrc_batch_plan *b, const std::vector<int32_t> &v, int64_t &off)
+{
+    off = (int64_t)b->blob.size();
+    b->blob.resize(csrc::align256(off + std::max<int64_t>(1, (int64_t)v.size() * 4)));
+    if (!v.empty()) std::memcpy(b->blob.data() + off, v.data(), v.size() * 4);
+}
+
+// OWNER batch: an owner plan per matrix (lane group G >= r, pull segments),
+// the (matrix, tile) items in matrix order and the eight equal-cost ranges,
+// one per XCD.  A tile's cost is its stored entries and rows times G.
+int owner_batch(csrc_batch_plan *b, int32_t nmat, const int32_t *n, const int32_t *const *ia,
+                const int32_t *const *ja, const int32_t *r, int32_t vdtype)
+{
+    std::vector<int64_t> cost;
+    for (int32_t m = 0; m < nmat; ++m) {
+        if (r[m] < 1 || r[m] > csrc::kMaxRhs || n[m] < 0) return CSRC_ERR_ARG;
+        csrc_plan_opts po;
+        csrc_plan_opts_default(CSRC_V_OWNER, &po);
+        po.tile_work = b->o.tile_work;
+        po.block = b->o.block;
+        po.ydtype = b->ydtype;
+        po.max_rhs = std::max(2, (int)r[m]);   // a lane group of at least four lanes
+        csrc_plan *p = nullptr;
+        int st = csrc_plan_create(n[m], ia[m], ja[m], vdtype, &po, &p);
+        if (st) return st;
+        b->plans.push_back(p);
+        b->n.push_back(n[m]);
+        b->r.push_back(r[m]);
+        b->part_off.push_back(0);
+        b->lds = std::max(b->lds, csrc::lds_owner_pull(p->max_tile_rows, p->mm_group));
+        for (int32_t t = 0; t < p->ntiles; ++t) {
+            const int64_t e = (int64_t)p->tile_k[t + 1] - p->tile_k[t];
+            const int64_t rows = (int64_t)p->tiles[t + 1] - p->tiles[t];
+            b->items.push_back(m);
+            b->items.push_back(t);
+            cost.push_back((2 * e + rows) * p->mm_group);
+        }
+    }
+    if (b->lds > csrc::kLdsBudget) return CSRC_ERR_UNSUPPORTED;
+    const int64_t nit = (int64_t)cost.size();
+    if (nit >= ((int64_t)1 << 31)) return CSRC_ERR_TOO_LARGE;
+    int64_t total = 0;
+    for (int64_t c : cost) total += c;
+    b->xbeg.assign(9, (int32_t)nit);
+    b->xbeg[0] = 0;
+    int64_t prefix = 0;
+    int x = 1;
+    for (int64_t i = 0; i < nit && x < 8; ++i) {
+        while (x < 8 && prefix * 8 >= (int64_t)x * total) b->xbeg[x++] = (int32_t)i;
+        prefix += cost[i];
+    }
+    for (int32_t m = 0; m < nmat; ++m) {
+        const csrc_plan *p = b->plans[m];
+        b->blob_off.push_back((int64_t)b->blob.size());
+        b->blob.insert(b->blob.end(), p->blob.begin(), p->blob.end());
+        b->blob.resize(csrc::align256((int64_t)b->blob.size()));
+    }
+    put_ints(b, b->items, b->off_items);
+    put_ints(b, b->mitems, b->off_mitems);
+    put_ints(b, b->xbeg, b->off_xbeg);
+    b->off_descs = (int64_t)b->blob.size();
+    b->off_parts = csrc::align256(b->off_descs + (int64_t)sizeof(csrc::MatDev) * std::max(1, nmat));
+    b->ws_bytes = b->off_parts;
+    return CSRC_OK;
+}
+
+}  // namespace
 
 extern "C" int csrc_batch_plan_create(int32_t nmat, const int32_t *n, const int32_t *const *ia,
                                       const int32_t *const *ja, const int32_t *r, int32_t vdtype,
@@ -22,8 +93,16 @@ extern "C" int csrc_batch_plan_create(int32_t nmat, const int32_t *n, const int3
         b->nmat = nmat;
         b->vdtype = vdtype;
         if (opts) b->o = *opts;
-        if (b->o.block == 0) b->o.block = 512;
+        b->variant = b->o.variant == 0 ? CSRC_V_OWNER : b->o.variant;
+        if (b->variant != CSRC_V_OWNER && b->variant != CSRC_V_PRIVATE) { delete b; return CSRC_ERR_ARG; }
+        if (b->o.block == 0) b->o.block = b->variant == CSRC_V_OWNER ? 256 : 512;
         b->ydtype = vdtype == CSRC_F64 ? CSRC_F64 : (b->o.ydtype == CSRC_F64 ? CSRC_F64 : CSRC_F32);
+        if (b->variant == CSRC_V_OWNER) {
+            int st = owner_batch(b, nmat, n, ia, ja, r, vdtype);
+            if (st) { delete b; return st; }
+            *out = b;
+            return CSRC_OK;
+        }
         const int acc = csrc::acc_bytes(vdtype);
         const int C = csrc::mm_columns(vdtype);
         struct Item { int32_t m, t; int64_t cost; };
@@ -75,13 +154,8 @@ extern "C" int csrc_batch_plan_create(int32_t nmat, const int32_t *n, const int3
             b->blob.insert(b->blob.end(), p->blob.begin(), p->blob.end());
             b->blob.resize(csrc::align256((int64_t)b->blob.size()));
         }
-        auto put_ints = [&](const std::vector<int32_t> &v, int64_t &off) {
-            off = (int64_t)b->blob.size();
-            b->blob.resize(csrc::align256(off + std::max<int64_t>(1, (int64_t)v.size() * 4)));
-            if (!v.empty()) std::memcpy(b->blob.data() + off, v.data(), v.size() * 4);
-        };
-        put_ints(b->items, b->off_items);
-        put_ints(b->mitems, b->off_mitems);
+        put_ints(b, b->items, b->off_items);
+        put_ints(b, b->mitems, b->off_mitems);
         b->off_descs = (int64_t)b->blob.size();
         b->off_parts = csrc::align256(b->off_descs + (int64_t)sizeof(csrc::MatDev) * std::max(1, nmat));
         b->ws_bytes = csrc::align256(b->off_parts + part_bytes);
@@ -131,6 +205,8 @@ extern "C" int csrc_batch_bind(const csrc_batch_plan *b, const csrc_matrix *A, c
             md.ldy = ldy[m];
             md.n = a.n;
             md.r = b->r[m];
+            md.g = b->variant == CSRC_V_OWNER ? p->mm_group : 0;
+            md.pad = 0;
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         int st = csrc::hip_status(hipMemcpyAsync(ws, b->blob.data(), b->blob.size(), hipMemcpyHostToDevice, s));

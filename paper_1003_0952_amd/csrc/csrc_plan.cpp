@@ -159,7 +159,13 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             int64_t parts = std::max<int64_t>(1, (total + p->o.tile_work - 1) / p->o.tile_work);
             if (parts > (int64_t)1 << 30) { delete p; return CSRC_ERR_TOO_LARGE; }
             nnz_partition(n, ia, (int32_t)parts, p->tiles);
-            cap_tile_rows(p->tiles, csrc::kMaxTileRows);
+            // the owner multi-column kernel keeps a tile's rows x r sums in LDS
+            int32_t cap = csrc::kMaxTileRows;
+            if (v == CSRC_V_OWNER) {
+                p->mm_group = csrc::mm_group(p->o.max_rhs);
+                cap = csrc::owner_mm_max_rows(p->mm_group);
+            }
+            cap_tile_rows(p->tiles, cap);
             // a tile is a non-empty block (more blocks than rows, or rows
             // heavier than a block's share, leave empty ones)
             p->tiles.erase(std::unique(p->tiles.begin(), p->tiles.end()), p->tiles.end());
@@ -356,9 +362,30 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
             }
             const int64_t em = std::max(p->max_tile_entries, p->max_pull_entries);
             p->lds_bytes = csrc::lds_owner(p->max_tile_rows, p->max_pull_rows, em, acc);
-            if (p->o.max_rhs > 1)
-                p->lds_bytes = std::max(p->lds_bytes, csrc::lds_owner_mm(p->max_tile_rows, p->max_pull_rows, em, acc,
-                                                                         csrc::mm_columns(vdtype)));
+            {
+                // pull segments (products with strided or several right-hand
+                // sides): for every row, each run of its entries (columns
+                // ascending) that falls into one tile is a segment of that tile;
+                // a tile's segments are in ascending row order
+                p->seg_ptr.assign(p->ntiles + 1, 0);
+                for (int32_t i = 0; i < n; ++i)
+                    for (int32_t q = ia[i]; q < ia[i + 1]; ++q)
+                        if (q == ia[i] || tile_of[ja[q]] != tile_of[ja[q - 1]]) p->seg_ptr[tile_of[ja[q]] + 1]++;
+                for (int32_t t = 0; t < p->ntiles; ++t) p->seg_ptr[t + 1] += p->seg_ptr[t];
+                p->segs.resize(p->seg_ptr[p->ntiles]);
+                std::vector<int32_t> sf(p->seg_ptr.begin(), p->seg_ptr.end() - 1);
+                for (int32_t i = 0; i < n; ++i) {
+                    int32_t q = ia[i];
+                    while (q < ia[i + 1]) {
+                        const int32_t tj = tile_of[ja[q]];
+                        int32_t e = q + 1;
+                        while (e < ia[i + 1] && tile_of[ja[e]] == tj) ++e;
+                        p->segs[sf[tj]++] = csrc::PullSeg{i, q, e, 0};
+                        q = e;
+                    }
+                }
+                p->lds_bytes = std::max(p->lds_bytes, csrc::lds_owner_pull(p->max_tile_rows, p->mm_group));
+            }
             if (p->lds_bytes > csrc::kLdsBudget) { delete p; return CSRC_ERR_UNSUPPORTED; }
         }
 
@@ -386,6 +413,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
         put(blob, p->t_mb_seg, p->mb_seg);
         put(blob, p->t_trec, p->trec);
         put(blob, p->t_crow, p->crow);
+        put(blob, p->t_seg_ptr, p->seg_ptr);
+        put(blob, p->t_segs, p->segs);
         p->blob_bytes = (int64_t)blob.size();
         p->t_partials.offset = p->blob_bytes;
         // the atomic merge of single products needs no partials
@@ -487,6 +516,8 @@ PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials)
     d.crow = (const int32_t *)at(p->t_crow);
     d.cptr = nullptr;
     d.partials = partials;
+    d.seg_ptr = (const int32_t *)at(p->t_seg_ptr);
+    d.segs = (const PullSeg *)at(p->t_segs);
     return d;
 }
 

@@ -1357,116 +1357,248 @@ __global__ __launch_bounds__(kMergeBlock) void k_batch_merge(const MatDev *__res
     }
 }
 
-template <class VT, class YT>
-__global__ __launch_bounds__(512) void k_owner_mm(PlanDev P, int64_t kend, const int32_t *__restrict__ ia,
-                                                  const int32_t *__restrict__ ja,
-                                                  const typename VT::V *__restrict__ ad,
-                                                  const typename VT::V *__restrict__ al,
-                                                  const typename VT::V *__restrict__ au,
-                                                  const typename VT::X *__restrict__ X, int64_t ldx,
-                                                  YT *__restrict__ Y, int64_t ldy, int r, int tmax, int pmax,
-                                                  int emax)
+// --------------------------------------------- OWNER, several right-hand sides
+//
+// Owner computes with the right-hand sides across lanes: a row's W columns
+// (W = 4G >= r, a power of two) are held by a group of G lanes, four columns
+// per lane.  Phase 1 gathers each own row in registers,
+//     acc = ad_i X[i, :] + sum_{q in row i} al_q X[ja_q, :],
+// and stores it into the tile's LDS sums.  Phase 2 walks the tile's pull
+// segments -- for every row p at or after the tile, the run of its entries
+// whose columns fall into the tile -- and adds au_q X[p, :] to the sums of
+// row ja_q with LDS atomics (the column-wise scatter of Fig. 2a, done by the
+// owner of the target).  Phase 3 stores the finished rows.  Every Y entry is
+// written once: no clearing, no partials, no global atomics, no merge pass.
+//
+// Memory instructions are what bound this kernel (each touches several
+// cache lines), so they are made wide: a lane reads its part of an x row as
+// 16-byte pieces -- FP64: columns {2c, 2c+1} and {W/2 + 2c, W/2 + 2c + 1},
+// so a group's first piece is one contiguous run of W/2 values; FP32: the
+// four columns 4c..4c+3 -- and a row's entries four at a time (ja as 16
+// bytes, FP64 values as 2 x 16, FP32 as 16).  A piece that would reach past
+// the last column, or a group of entries past the row's end, is read value
+// by value instead, so no load leaves its row or its array.
+
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef int i4u __attribute__((ext_vector_type(4), aligned(4)));
+
+// Four entries from q (entries from qe on are absent: j = -1, value 0):
+// column indices and values of vals, as the accumulator type.
+template <class VT>
+__device__ __forceinline__ void entries4(const int32_t *__restrict__ ja, const typename VT::V *__restrict__ vals,
+                                         int q, int qe, int (&j)[4], typename VT::A (&a)[4])
+{
+    using V = typename VT::V;
+    using A = typename VT::A;
+    if (q + 3 < qe) {
+        const i4u jj = *reinterpret_cast<const i4u *>(ja + q);
+        j[0] = jj.x;
+        j[1] = jj.y;
+        j[2] = jj.z;
+        j[3] = jj.w;
+        if constexpr (std::is_same<V, double>::value) {
+            const d2u v0 = *reinterpret_cast<const d2u *>(vals + q);
+            const d2u v1 = *reinterpret_cast<const d2u *>(vals + q + 2);
+            a[0] = v0.x;
+            a[1] = v0.y;
+            a[2] = v1.x;
+            a[3] = v1.y;
+        } else if constexpr (std::is_same<V, float>::value) {
+            const f4u v = *reinterpret_cast<const f4u *>(vals + q);
+            a[0] = v.x;
+            a[1] = v.y;
+            a[2] = v.z;
+            a[3] = v.w;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = (A)ldv(vals, q + u);
+        }
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const bool ok = q + u < qe;
+        j[u] = ok ? ja[q + u] : -1;
+        a[u] = ok ? (A)ldv(vals, q + u) : A(0);
+    }
+}
+
+// One owner tile t with r columns (r <= 4G).  s_y: LDS, rows x owner_mm_ld(4G)
+// FP64 sums.  Called by every thread of the workgroup.
+template <class VT, class YT, int G>
+__device__ __forceinline__ void owner_tile_pull(const PlanDev &P, int t, const int32_t *__restrict__ ia,
+                                                const int32_t *__restrict__ ja,
+                                                const typename VT::V *__restrict__ ad,
+                                                const typename VT::V *__restrict__ al,
+                                                const typename VT::V *__restrict__ au,
+                                                const typename VT::X *__restrict__ X, int64_t ldx,
+                                                YT *__restrict__ Y, int64_t ldy, int r, double *s_y)
 {
     using A = typename VT::A;
-    using S = typename VT::S;
-    constexpr int C = MmCols<VT>::C;
-    extern __shared__ __align__(16) unsigned char lds[];
-    A *s_x = reinterpret_cast<A *>(lds);
-    A *s_xp = s_x + (int64_t)tmax * C;
-    const int64_t xbytes = align16(((int64_t)tmax + pmax) * C * sizeof(A));
-    S *s_y = reinterpret_cast<S *>(lds + xbytes);
-    uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + xbytes + align16((int64_t)tmax * C * sizeof(S)));
-    const int tid = threadIdx.x, B = blockDim.x;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    using Xt = typename VT::X;
+    constexpr int W = 4 * G;                  // columns per row
+    constexpr int LD = owner_mm_ld(W);
+    constexpr bool kX64 = sizeof(Xt) == 8;
+    static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "lane group");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int lc = lane & (G - 1);
+    const int grp = tid / G, ngrp = (int)blockDim.x / G;
+    int col[4];                               // the columns this lane holds
+#pragma unroll
+    for (int v = 0; v < 4; ++v) col[v] = kX64 ? (v >> 1) * (W / 2) + 2 * lc + (v & 1) : 4 * lc + v;
     const int r0 = P.tiles[t], r1 = P.tiles[t + 1], T = r1 - r0;
-    const int k0 = P.tile_k[t], k1 = P.tile_k[t + 1], kb = k0 & ~1;
-    const int half = 2 * B;
-    const int p0 = P.iv_ptr[t], p1 = P.iv_ptr[t + 1];
-    for (int cc = 0; cc < r; cc += C) {
-        const int nc = min(C, r - cc);
-        __syncthreads();
-        for (int e = tid; e < T * C; e += B) {
-            const int i = e / C, c = e % C;
-            const A xv = c < nc ? (A)X[(int64_t)(r0 + i) * ldx + cc + c] : A(0);
-            s_x[e] = xv;
-            s_y[e] = (A)ldv(ad, r0 + i) * xv;
-        }
-        fill_row_ids(ia, r0, r1, kb, s_rid);
-        __syncthreads();
-        settle_loads();
-        const Entries<VT, false> E(ja, al, au, kb, k1);
-        Batch<VT, true, true, false> cur;
-        cur.load(kb + 2 * tid, E);
-        for (int qb = kb + 2 * tid; qb < k1; qb += 2 * half) {
-            Batch<VT, true, true, false> nxt;
-            if (qb + 2 * half < k1) nxt.load(qb + 2 * half, E);
+    auto xrow = [&](int row, A(&o)[4]) {
+        const Xt *p = X + (int64_t)row * ldx;
+        if constexpr (kX64) {
 #pragma unroll
-            for (int sp = 0; sp < 2; ++sp) {
-                const int q = qb + half * sp;
-                if (q >= k1) continue;
-                const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - kb));
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int row = (int)((rv >> (16 * h)) & 0xFFFF);
-                    if (row == (int)kNoRow) continue;
-                    const int j = cur.j[sp][h];
-                    const A a = cur.a[sp][h], u = cur.u[sp][h];
-                    if (j >= r0) {
-#pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            atomic_add(&s_y[(j - r0) * C + c], u * s_x[row * C + c]);
-                            atomic_add(&s_y[row * C + c], a * s_x[(j - r0) * C + c]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            const A xj = c < nc ? (A)X[(int64_t)j * ldx + cc + c] : A(0);
-                            atomic_add(&s_y[row * C + c], a * xj);
-                        }
-                    }
+            for (int h = 0; h < 2; ++h) {
+                const int b = col[2 * h];
+                if (b + 1 < r) {
+                    const d2u v = *reinterpret_cast<const d2u *>(p + b);
+                    o[2 * h] = v.x;
+                    o[2 * h + 1] = v.y;
+                } else {
+                    o[2 * h] = b < r ? (A)p[b] : A(0);
+                    o[2 * h + 1] = A(0);
                 }
             }
-            cur = nxt;
-        }
-        for (int e = p0; e < p1; ++e) {
-            const int pa = P.iv_row[e], L = P.iv_len[e];
-            const int qa = ia[pa], qe = ia[pa + L], qbase = qa & ~1;
-            __syncthreads();
-            for (int i = tid; i < L * C; i += B) {
-                const int ii = i / C, c = i % C;
-                s_xp[i] = c < nc ? (A)X[(int64_t)(pa + ii) * ldx + cc + c] : A(0);
+        } else {
+            const int b = col[0];
+            if (b + 3 < r) {
+                const f4u v = *reinterpret_cast<const f4u *>(p + b);
+                o[0] = v.x;
+                o[1] = v.y;
+                o[2] = v.z;
+                o[3] = v.w;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = b + v < r ? (A)p[b + v] : A(0);
             }
-            fill_row_ids(ia, pa, pa + L, qbase, s_rid);
-            __syncthreads();
-            settle_loads();
-            const Entries<VT, false> Ep(ja, al, au, qbase, qe);
-            for (int qb = qbase + 2 * tid; qb < qe; qb += 2 * half) {
+        }
+    };
+    __syncthreads();   // the workgroup's previous tile has left the LDS
+
+    // phase 1: own rows, row-wise gather in registers; the next four
+    // entries load while the current four's x rows do
+    for (int i = grp; i < T; i += ngrp) {
+        const int row = r0 + i;
+        const int q0 = ia[row], q1 = ia[row + 1];
+        A acc[4];
+        {
+            A xi[4];
+            xrow(row, xi);
+            const A d = (A)ldv(ad, row);
 #pragma unroll
-                for (int sp = 0; sp < 2; ++sp) {
-                    const int q = qb + half * sp;
-                    if (q >= qe) continue;
-                    int jj[2];
-                    A uu[2] = {A(0), A(0)};
-                    Ep.j2(q, jj);
-                    const uint32_t rv = *reinterpret_cast<const uint32_t *>(s_rid + (q - qbase));
-                    const bool t0 = (rv & 0xFFFF) != kNoRow && jj[0] >= r0 && jj[0] < r1;
-                    const bool t1 = (rv >> 16) != kNoRow && jj[1] >= r0 && jj[1] < r1;
-                    if (t0 || t1) Ep.au2(q, uu);
+            for (int v = 0; v < 4; ++v) acc[v] = d * xi[v];
+        }
+        int jn[4];
+        A an[4];
+        entries4<VT>(ja, al, q0, q1, jn, an);
+        for (int qb = q0; qb < q1; qb += 4) {
+            int jc[4];
+            A ac[4], xv[4][4];
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int row = (int)((rv >> (16 * h)) & 0xFFFF);
-                        const int j = jj[h];
-                        if (!(h ? t1 : t0)) continue;
+            for (int u = 0; u < 4; ++u) {
+                jc[u] = jn[u];
+                ac[u] = an[u];
+                if (jc[u] >= 0) {
+                    xrow(jc[u], xv[u]);
+                } else {
 #pragma unroll
-                        for (int c = 0; c < C; ++c) atomic_add(&s_y[(j - r0) * C + c], uu[h] * s_xp[row * C + c]);
-                    }
+                    for (int v = 0; v < 4; ++v) xv[u][v] = A(0);
                 }
             }
+            if (qb + 4 < q1) entries4<VT>(ja, al, qb + 4, q1, jn, an);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += ac[u] * xv[u][v];
         }
-        __syncthreads();
-        for (int e = tid; e < T * C; e += B) {
-            const int i = e / C, c = e % C;
-            if (c < nc) Y[(int64_t)(r0 + i) * ldy + cc + c] = (YT)s_y[e];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (col[v] < r) s_y[i * LD + col[v]] = (double)acc[v];
+    }
+    __syncthreads();
+
+    // phase 2: the scatters into the tile, pulled from the rows that make them
+    const int s0 = P.seg_ptr[t], s1 = P.seg_ptr[t + 1];
+    for (int g = s0 + grp; g < s1; g += ngrp) {
+        const PullSeg sg = P.segs[g];
+        A xp[4];
+        xrow(sg.row, xp);
+        for (int qb = sg.q0; qb < sg.q1; qb += 4) {
+            int jc[4];
+            A uc[4];
+            entries4<VT>(ja, au, qb, sg.q1, jc, uc);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (jc[u] >= 0) {
+                    const int base = (jc[u] - r0) * LD;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (col[v] < r) atomic_add(&s_y[base + col[v]], (double)(uc[u] * xp[v]));
+                }
+        }
+    }
+    __syncthreads();
+
+    // phase 3: the finished rows (consecutive threads on consecutive columns)
+    for (int e = tid; e < T * W; e += blockDim.x) {
+        const int i = e / W, cc = e % W;
+        if (cc < r) Y[(int64_t)(r0 + i) * ldy + cc] = (YT)s_y[i * LD + cc];
+    }
+}
+
+// Waves per SIMD the owner multi-column kernels are compiled for: the
+// kernels wait on memory most of the time and need every wave, so eight
+// (64 VGPRs) for FP32 and BF16 values; six for FP64 (at most 85 VGPRs: 64
+// would spill).
+template <class VT> struct PullWaves { static constexpr int value = 8; };
+template <> struct PullWaves<F64T> { static constexpr int value = 6; };
+
+template <class VT, class YT, int G>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PullWaves<VT>::value))) void k_owner_pull(PlanDev P, const int32_t *__restrict__ ia,
+                                                    const int32_t *__restrict__ ja,
+                                                    const typename VT::V *__restrict__ ad,
+                                                    const typename VT::V *__restrict__ al,
+                                                    const typename VT::V *__restrict__ au,
+                                                    const typename VT::X *__restrict__ X, int64_t ldx,
+                                                    YT *__restrict__ Y, int64_t ldy, int r)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    owner_tile_pull<VT, YT, G>(P, xcd_tile(blockIdx.x, gridDim.x), ia, ja, ad, al, au, X, ldx, Y, ldy, r,
+                               reinterpret_cast<double *>(lds));
+}
+
+// Batched owner products: the work list holds (matrix, tile) items in matrix
+// order, cut into 8 ranges of equal cost (xbeg[0..8]); the workgroups of XCD x
+// (blockIdx mod 8) walk range x with a stride, so neighbouring tiles of one
+// matrix share that XCD's L2.  The grid is a multiple of 8.
+template <class VT, class YT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PullWaves<VT>::value))) void k_batch_pull(const MatDev *__restrict__ mats, const int2 *__restrict__ items,
+                                                    const int32_t *__restrict__ xbeg, int transpose)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    using V = typename VT::V;
+    using Xt = typename VT::X;
+    double *s_y = reinterpret_cast<double *>(lds);
+    const int x = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int e1 = xbeg[x + 1];
+    for (int it = xbeg[x] + (int)(blockIdx.x >> 3); it < e1; it += per) {
+        const int2 w = items[it];
+        const MatDev &M = mats[w.x];
+        const V *al = static_cast<const V *>(transpose ? M.au : M.al);
+        const V *au = static_cast<const V *>(transpose ? M.al : M.au);
+        const V *ad = static_cast<const V *>(M.ad);
+        const Xt *Xm = static_cast<const Xt *>(M.X);
+        YT *Ym = static_cast<YT *>(M.Y);
+        // M.g columns per row (4..32): groups of M.g / 4 lanes
+        switch (M.g) {
+        case 4: owner_tile_pull<VT, YT, 1>(M.P, w.y, M.ia, M.ja, ad, al, au, Xm, M.ldx, Ym, M.ldy, M.r, s_y); break;
+        case 8: owner_tile_pull<VT, YT, 2>(M.P, w.y, M.ia, M.ja, ad, al, au, Xm, M.ldx, Ym, M.ldy, M.r, s_y); break;
+        case 16: owner_tile_pull<VT, YT, 4>(M.P, w.y, M.ia, M.ja, ad, al, au, Xm, M.ldx, Ym, M.ldy, M.r, s_y); break;
+        default: owner_tile_pull<VT, YT, 8>(M.P, w.y, M.ia, M.ja, ad, al, au, Xm, M.ldx, Ym, M.ldy, M.r, s_y); break;
         }
     }
 }
@@ -1612,11 +1744,19 @@ static int launch_variant(const csrc_plan *p, const csrc_matrix *A, const void *
             if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
             kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, y, tmax, pmax, emax);
         } else {
-            const size_t lds = (size_t)lds_owner_mm(tmax, pmax, emax, sizeof(Acc), MmCols<VT>::C);
-            if (lds > (size_t)kLdsBudget) return CSRC_ERR_UNSUPPORTED;
-            auto kern = k_owner_mm<VT, YT>;
-            if (set_lds((const void *)kern, lds)) return CSRC_ERR_HIP;
-            kern<<<p->ntiles, B, lds, s>>>(P, A->k, A->ia, A->ja, ad, al, au, x, ldx, y, ldy, r, tmax, pmax, emax);
+            // lanes over the right-hand sides: the plan's lane group covers
+            // max_rhs >= r columns
+            const int g = p->mm_group;
+            const size_t lds = (size_t)lds_owner_pull(tmax, g);
+            if (g < 4 || g > 32 || r > g || lds > (size_t)kLdsBudget) return CSRC_ERR_PLAN;
+            const void *kern = g == 4 ? (const void *)k_owner_pull<VT, YT, 1>
+                             : g == 8 ? (const void *)k_owner_pull<VT, YT, 2>
+                             : g == 16 ? (const void *)k_owner_pull<VT, YT, 4>
+                                       : (const void *)k_owner_pull<VT, YT, 8>;
+            if (set_lds(kern, lds)) return CSRC_ERR_HIP;
+            void *args[] = {(void *)&P, (void *)&A->ia, (void *)&A->ja, (void *)&ad, (void *)&al, (void *)&au,
+                            (void *)&x, (void *)&ldx, (void *)&y, (void *)&ldy, (void *)&r};
+            if (hip_status(hipLaunchKernel(kern, dim3(p->ntiles), dim3(B), args, lds, s))) return CSRC_ERR_HIP;
         }
         break;
     }
@@ -1974,7 +2114,7 @@ namespace csrc {
 
 struct BatchLaunch {
     const void *tiles_fn = nullptr;
-    const void *merge_fn = nullptr;
+    const void *merge_fn = nullptr;   // PRIVATE only
     int grid = 0, merge_grid = 0, block = 512;
     size_t lds = 0;
 };
@@ -1989,9 +2129,13 @@ static int device_cus()
 }
 
 template <class VT, class YT>
-static void batch_fns(BatchLaunch &L)
+static void batch_fns(BatchLaunch &L, bool owner)
 {
     using Acc = typename VT::A;
+    if (owner) {
+        L.tiles_fn = (const void *)k_batch_pull<VT, YT>;
+        return;
+    }
     L.tiles_fn = (const void *)k_batch_tiles<VT, YT>;
     if (std::is_same<YT, double>::value)
         L.merge_fn = (const void *)k_batch_merge<Acc, YT, double, false>;
@@ -2001,25 +2145,88 @@ static void batch_fns(BatchLaunch &L)
 
 static int batch_launch_config(const csrc_batch_plan *b, BatchLaunch &L)
 {
+    const bool owner = b->variant == CSRC_V_OWNER;
     switch (b->vdtype) {
-    case CSRC_F64: batch_fns<F64T, double>(L); break;
+    case CSRC_F64: batch_fns<F64T, double>(L, owner); break;
     case CSRC_F32:
-        if (b->ydtype == CSRC_F64) batch_fns<F32T, double>(L); else batch_fns<F32T, float>(L);
+        if (b->ydtype == CSRC_F64) batch_fns<F32T, double>(L, owner); else batch_fns<F32T, float>(L, owner);
         break;
     default:
-        if (b->ydtype == CSRC_F64) batch_fns<B16T, double>(L); else batch_fns<B16T, float>(L);
+        if (b->ydtype == CSRC_F64) batch_fns<B16T, double>(L, owner); else batch_fns<B16T, float>(L, owner);
     }
     L.block = b->o.block;
     L.lds = (size_t)b->lds;
     const int cus = device_cus();
-    const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, kLdsBudget / std::max<int64_t>(1, b->lds)));
     const int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
-    L.grid = b->o.grid > 0 ? b->o.grid : std::max(1, std::min(nitems, cus * per_cu));
-    L.merge_grid = std::max(1, std::min(nm, cus * 8));
+    if (owner) {
+        // one workgroup per slot that can be resident (registers, LDS and
+        // waves of a CU): each holds a fixed share of its XCD's range, so a
+        // workgroup that had to wait for a slot would finish its share late
+        if (L.lds > 65536 &&
+            hip_status(hipFuncSetAttribute(L.tiles_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds)))
+            return CSRC_ERR_HIP;
+        int per_cu = 0;
+        int st = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, L.tiles_fn, L.block, L.lds));
+        if (st) return st;
+        const int g = b->o.grid > 0 ? b->o.grid : cus * std::max(1, per_cu);
+        L.grid = std::max(8, g & ~7);   // a multiple of 8: one share per XCD
+        return CSRC_OK;
+    } else {
+        const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, kLdsBudget / std::max<int64_t>(1, b->lds)));
+        L.grid = b->o.grid > 0 ? b->o.grid : std::max(1, std::min(nitems, cus * per_cu));
+        L.merge_grid = std::max(1, std::min(nm, cus * 8));
+    }
     if (L.lds > 65536)
         return hip_status(hipFuncSetAttribute(L.tiles_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     return CSRC_OK;
 }
+
+// Kernel arguments of a batch launch (kept alive for the launch or the graph
+// node that copies them).
+struct BatchArgs {
+    const MatDev *mats;
+    const int2 *items, *mitems;
+    const int32_t *xbeg;
+    int nitems, nm, tr, smax, emax;
+    void *tiles[6];
+    void *merge[3];
+    int ntiles_args = 0;
+
+    BatchArgs(const csrc_batch_plan *b, char *ws, int transpose)
+    {
+        mats = reinterpret_cast<const MatDev *>(ws + b->off_descs);
+        items = reinterpret_cast<const int2 *>(ws + b->off_items);
+        mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
+        xbeg = reinterpret_cast<const int32_t *>(ws + b->off_xbeg);
+        nitems = (int)(b->items.size() / 2);
+        nm = (int)(b->mitems.size() / 2);
+        tr = transpose ? 1 : 0;
+        smax = b->smax;
+        emax = b->emax;
+        if (b->variant == CSRC_V_OWNER) {
+            // k_batch_pull(mats, items, xbeg, transpose)
+            tiles[0] = (void *)&mats;
+            tiles[1] = (void *)&items;
+            tiles[2] = (void *)&xbeg;
+            tiles[3] = (void *)&tr;
+            ntiles_args = 4;
+        } else {
+            // k_batch_tiles(mats, items, nitems, transpose, smax, emax)
+            tiles[0] = (void *)&mats;
+            tiles[1] = (void *)&items;
+            tiles[2] = (void *)&nitems;
+            tiles[3] = (void *)&tr;
+            tiles[4] = (void *)&smax;
+            tiles[5] = (void *)&emax;
+            ntiles_args = 6;
+        }
+        merge[0] = (void *)&mats;
+        merge[1] = (void *)&mitems;
+        merge[2] = (void *)&nm;
+    }
+    BatchArgs(const BatchArgs &) = delete;
+    BatchArgs &operator=(const BatchArgs &) = delete;
+};
 
 }  // namespace csrc
 
@@ -2029,22 +2236,15 @@ extern "C" int csrc_batch_run(const csrc_batch_plan *b, int32_t transpose, void 
     using namespace csrc;
     if (!b) return CSRC_ERR_ARG;
     if (!workspace || ws_bytes < b->ws_bytes) return CSRC_ERR_WORKSPACE;
-    const int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
-    if (nitems == 0) return CSRC_OK;
+    if (b->items.empty()) return CSRC_OK;
     BatchLaunch L;
     int st = batch_launch_config(b, L);
     if (st) return st;
-    char *ws = static_cast<char *>(workspace);
-    const MatDev *mats = reinterpret_cast<const MatDev *>(ws + b->off_descs);
-    const int2 *items = reinterpret_cast<const int2 *>(ws + b->off_items);
-    const int2 *mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
-    int tr = transpose ? 1 : 0, smax = b->smax, emax = b->emax;
-    void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&smax, (void *)&emax};
+    BatchArgs a(b, static_cast<char *>(workspace), transpose);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    st = hip_status(hipLaunchKernel(L.tiles_fn, dim3(L.grid), dim3(L.block), args1, L.lds, s));
-    if (st || nm == 0) return st;
-    void *args2[] = {(void *)&mats, (void *)&mitems, (void *)&nm};
-    return hip_status(hipLaunchKernel(L.merge_fn, dim3(L.merge_grid), dim3(kMergeBlock), args2, 0, s));
+    st = hip_status(hipLaunchKernel(L.tiles_fn, dim3(L.grid), dim3(L.block), a.tiles, L.lds, s));
+    if (st || !L.merge_fn || a.nm == 0) return st;
+    return hip_status(hipLaunchKernel(L.merge_fn, dim3(L.merge_grid), dim3(kMergeBlock), a.merge, 0, s));
 }
 
 extern "C" int csrc_spmv_batched(const csrc_batch_plan *b, const csrc_matrix *A, const void *const *X,
@@ -2073,34 +2273,26 @@ extern "C" int csrc_batch_graph_create(const csrc_batch_plan *b, int32_t transpo
     BatchLaunch L;
     int st = batch_launch_config(b, L);
     if (st) return st;
-    char *ws = static_cast<char *>(workspace);
-    const MatDev *mats = reinterpret_cast<const MatDev *>(ws + b->off_descs);
-    const int2 *items = reinterpret_cast<const int2 *>(ws + b->off_items);
-    const int2 *mitems = reinterpret_cast<const int2 *>(ws + b->off_mitems);
-    int nitems = (int)(b->items.size() / 2), nm = (int)(b->mitems.size() / 2);
-    int tr = transpose ? 1 : 0, smax = b->smax, emax = b->emax;
+    BatchArgs a(b, static_cast<char *>(workspace), transpose);
     hipGraph_t g = nullptr;
     st = hip_status(hipGraphCreate(&g, 0));
     if (st) return st;
     hipGraphNode_t n1 = nullptr, n2 = nullptr;
-    if (nitems > 0) {
-        void *args1[] = {(void *)&mats, (void *)&items, (void *)&nitems, (void *)&tr, (void *)&smax,
-                         (void *)&emax};
+    if (a.nitems > 0) {
         hipKernelNodeParams k1{};
         k1.func = const_cast<void *>(L.tiles_fn);
         k1.gridDim = dim3(L.grid);
         k1.blockDim = dim3(L.block);
         k1.sharedMemBytes = (unsigned)L.lds;
-        k1.kernelParams = args1;
+        k1.kernelParams = a.tiles;
         st = hip_status(hipGraphAddKernelNode(&n1, g, nullptr, 0, &k1));
-        if (!st && nm > 0) {
-            void *args2[] = {(void *)&mats, (void *)&mitems, (void *)&nm};
+        if (!st && L.merge_fn && a.nm > 0) {
             hipKernelNodeParams k2{};
             k2.func = const_cast<void *>(L.merge_fn);
             k2.gridDim = dim3(L.merge_grid);
             k2.blockDim = dim3(kMergeBlock);
             k2.sharedMemBytes = 0;
-            k2.kernelParams = args2;
+            k2.kernelParams = a.merge;
             st = hip_status(hipGraphAddKernelNode(&n2, g, &n1, 1, &k2));
         }
     }

@@ -62,11 +62,35 @@ inline int64_t lds_private_mm(int64_t smax, int64_t emax, int64_t ivmax, int acc
 {
     return lds_xs((int64_t)mm_ld(smax) * C, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
 }
-inline int64_t lds_owner_mm(int64_t tmax, int64_t pmax, int64_t emax, int acc, int C)
-{
-    return align16((tmax + pmax) * C * acc) + align16(tmax * C * kSumBytes) + align16((emax + 4) * 2);
-}
 inline int mm_columns(int32_t vdtype) { return vdtype == CSRC_F64 ? 4 : 8; }
+
+// Owner-computes multi-column kernel: a row's W columns (W a power of two,
+// 4..32, at least r) are held by W / 4 lanes, four columns each; a tile's
+// sums take rows x (W + 1) FP64 values of LDS (the odd leading dimension
+// spreads the rows of concurrent groups over the banks), at most kOwnerMmLds
+// bytes, so that four workgroups share a compute unit's 160 KiB.
+constexpr int64_t kOwnerMmLds = 36 * 1024;
+constexpr int mm_group(int r)
+{
+    int g = 4;
+    while (g < r) g <<= 1;
+    return g;
+}
+constexpr int owner_mm_ld(int w) { return w + 1; }
+constexpr int owner_mm_max_rows(int g)
+{
+    return (int)(kOwnerMmLds / ((int64_t)owner_mm_ld(g) * 8)) < kMaxTileRows
+               ? (int)(kOwnerMmLds / ((int64_t)owner_mm_ld(g) * 8))
+               : kMaxTileRows;
+}
+inline int64_t lds_owner_pull(int64_t tmax, int g) { return tmax * owner_mm_ld(g) * 8; }
+
+// A pull segment of an owner tile: entries [q0, q1) of row `row` (a row at
+// or after the tile's first row) whose columns lie in the tile, i.e. the
+// scatters row `row` makes into the tile.  16 bytes, read with one load.
+struct alignas(16) PullSeg {
+    int32_t row, q0, q1, pad;
+};
 
 // A table placed in the device workspace.
 struct Table {
@@ -111,6 +135,8 @@ struct PlanDev {
     const int32_t *crow;       // rows sorted by colour
     const int32_t *cptr;       // colour class boundaries (host copy used for launches)
     void *partials;            // partial buffer (PRIVATE)
+    const int32_t *seg_ptr;    // OWNER: pull segments of each tile
+    const PullSeg *segs;
 };
 
 // One bound matrix of a batch (written into the workspace by
@@ -129,6 +155,8 @@ struct MatDev {
     int64_t ldy;
     int32_t n;
     int32_t r;
+    int32_t g;        // OWNER batches: columns per row W of the multi-column kernel
+    int32_t pad;
 };
 
 // Parameter layout of the selector network (12-H-H-K perceptron): offsets
@@ -178,9 +206,12 @@ struct csrc_plan {
     std::vector<csrc::TileRec> trec;
     std::vector<int64_t> iv_goff;
     std::vector<int32_t> color, crow, cptr;
+    std::vector<int32_t> seg_ptr;          // OWNER: pull segments per tile
+    std::vector<csrc::PullSeg> segs;
+    int32_t mm_group = 0;                  // OWNER: columns per row W of the multi-column kernel
     // layout of the workspace
     csrc::Table t_tiles, t_tile_k, t_iv_ptr, t_iv_row, t_iv_len, t_iv_slot, t_iv_goff,
-        t_mb_ptr, t_mb_seg, t_trec, t_crow, t_partials;
+        t_mb_ptr, t_mb_seg, t_trec, t_crow, t_seg_ptr, t_segs, t_partials;
     int64_t blob_bytes = 0;      // bytes of uploaded tables (prefix of workspace)
     int64_t ws_bytes = 0;
     std::vector<char> blob;      // host image of the uploaded tables
@@ -208,12 +239,14 @@ struct csrc_batch_plan {
     std::vector<int32_t> n, r;
     std::vector<int64_t> blob_off;   // table image of matrix m in the workspace
     std::vector<int64_t> part_off;   // partial slots of matrix m (bytes, from off_parts)
-    std::vector<int32_t> items;      // (matrix, tile) pairs, decreasing cost
-    std::vector<int32_t> mitems;     // (matrix, merge block) pairs
+    int32_t variant = CSRC_V_OWNER;  // OWNER (one pull kernel) or PRIVATE (tiles + merge)
+    std::vector<int32_t> items;      // (matrix, tile) pairs: PRIVATE decreasing cost, OWNER matrix order
+    std::vector<int32_t> mitems;     // (matrix, merge block) pairs (PRIVATE)
+    std::vector<int32_t> xbeg;       // OWNER: 9 item boundaries, one range of equal cost per XCD
     int32_t smax = 0, emax = 0, ivmax = 0;   // largest rows + slots, entries, intervals of a tile
     int64_t lds = 0;
     std::vector<char> blob;          // tables + work lists (uploaded by bind)
-    int64_t off_items = 0, off_mitems = 0, off_descs = 0, off_parts = 0, ws_bytes = 0;
+    int64_t off_items = 0, off_mitems = 0, off_xbeg = 0, off_descs = 0, off_parts = 0, ws_bytes = 0;
     ~csrc_batch_plan()
     {
         for (auto *p : plans) delete p;

@@ -34,13 +34,14 @@ DEFAULT = 1      # the fixed choice without a selector: private, 8192, 256 threa
 FALLBACK = 7     # ... or atomic, 8192, 512 threads where private cannot run
 PLAIN = 9        # ... or the plain kernel, which runs every matrix
 
-# Batched products (one persistent launch over many matrices): work item
-# size and threads per workgroup, timed on the whole batch.
+# Batched products (one persistent launch over many matrices): tile form,
+# work item size and threads per workgroup, timed on the whole batch.
 BATCH_CANDIDATES = [
-    {"tile_work": 4096, "block": 256},
-    {"tile_work": 8192, "block": 256},
-    {"tile_work": 8192, "block": 512},
-    {"tile_work": 16384, "block": 512},
+    {"variant": "owner", "tile_work": 4096, "block": 256},
+    {"variant": "owner", "tile_work": 4096, "block": 512},
+    {"variant": "owner", "tile_work": 8192, "block": 512},
+    {"variant": "owner", "tile_work": 16384, "block": 512},
+    {"variant": "private", "tile_work": 16384, "block": 512},
 ]
 
 

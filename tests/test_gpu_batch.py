@@ -29,14 +29,19 @@ def setup(C, torch, batch, dtype):
     return mats, Xs
 
 
+BATCH_VARIANTS = ["owner", "private"]
+
+
+@pytest.mark.parametrize("variant", BATCH_VARIANTS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("transpose", [False, True])
-def test_batched_matches_oracle(dtype, transpose):
+def test_batched_matches_oracle(dtype, transpose, variant):
     import torch
     import paper_1003_0952_amd as C
     batch = make_batch(24)
     mats, Xs = setup(C, torch, batch, dtype)
-    bp = C.BatchPlan(mats, [X.shape[1] for _, X in batch], ydtype="f64" if dtype == "f64" else "f32")
+    bp = C.BatchPlan(mats, [X.shape[1] for _, X in batch], ydtype="f64" if dtype == "f64" else "f32",
+                     variant=variant)
     Ys = [torch.full((a.n, X.shape[1]), float("nan"), dtype=bp.ytorch, device="cuda") for a, X in batch]
     (C.csrc_spmv_t_batched if transpose else C.csrc_spmv_batched)(bp, Xs, Ys)
     torch.cuda.synchronize()
@@ -58,17 +63,18 @@ def test_batched_matches_oracle(dtype, transpose):
                 assert np.all(np.abs(got[:, j] - ref) <= bound)
 
 
-def test_batched_integer_equals_single_products():
+@pytest.mark.parametrize("variant", BATCH_VARIANTS)
+def test_batched_integer_equals_single_products(variant):
     import torch
     import paper_1003_0952_amd as C
     batch = make_batch(16, kind="int")
     mats, Xs = setup(C, torch, batch, "f64")
-    bp = C.BatchPlan(mats, [X.shape[1] for _, X in batch])
+    bp = C.BatchPlan(mats, [X.shape[1] for _, X in batch], variant=variant)
     Ys = [torch.empty((a.n, X.shape[1]), dtype=torch.float64, device="cuda") for a, X in batch]
     C.csrc_spmv_batched(bp, Xs, Ys)
     torch.cuda.synchronize()
     for (a, X), A, Xt, Y in zip(batch, mats, Xs, Ys):
-        plan = C.Plan(A, "private", max_rhs=X.shape[1])
+        plan = C.Plan(A, variant, max_rhs=X.shape[1])
         Ysingle = torch.empty_like(Y)
         C.csrc_spmm(A, plan, Xt, Ysingle)
         torch.cuda.synchronize()
@@ -76,12 +82,13 @@ def test_batched_integer_equals_single_products():
         assert np.array_equal(Y.cpu().numpy(), R.spmm(oracle_csrc(a), X))
 
 
-def test_graph_replay_equals_direct_launch():
+@pytest.mark.parametrize("variant", BATCH_VARIANTS)
+def test_graph_replay_equals_direct_launch(variant):
     import torch
     import paper_1003_0952_amd as C
     batch = make_batch(20)
     mats, Xs = setup(C, torch, batch, "f64")
-    bp = C.BatchPlan(mats, [X.shape[1] for _, X in batch])
+    bp = C.BatchPlan(mats, [X.shape[1] for _, X in batch], variant=variant)
     Ys = [torch.zeros((a.n, X.shape[1]), dtype=torch.float64, device="cuda") for a, X in batch]
     bp.bind(Xs, Ys)
     bp.run()

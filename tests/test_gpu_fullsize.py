@@ -288,7 +288,7 @@ def batch_out(lib, batch_members, request):
         mats.append(A)
         Xs.append(torch.from_numpy(X).to("cuda", A.xdtype))
     rs = [X.shape[1] for _, X in batch_members]
-    kw = {"tile_work": 16384, "block": 512} if dtype == "f64" else {"tile_work": 8192, "block": 512}
+    kw = {"variant": "owner", "tile_work": 16384, "block": 512}
     ydt = "f64" if dtype == "f64" else "f32"
     bp = C.BatchPlan(mats, rs, ydtype=ydt, **kw)
     Ys = [torch.empty((A.n, r), dtype=bp.ytorch, device="cuda") for A, r in zip(mats, rs)]
