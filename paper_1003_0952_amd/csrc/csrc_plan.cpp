@@ -122,7 +122,8 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
     if (vdtype < CSRC_F64 || vdtype > CSRC_BF16) return CSRC_ERR_ARG;
     const csrc_plan_opts &o = *opts;
     if (o.variant < 0 || o.variant >= CSRC_V_COUNT) return CSRC_ERR_ARG;
-    if (o.block != 0 && (o.block < 64 || o.block > 512 || o.block % 64)) return CSRC_ERR_ARG;
+    if (o.block != 0 && (o.block < 64 || o.block > (o.variant == CSRC_V_OWNER ? 1024 : 512) || o.block % 64))
+        return CSRC_ERR_ARG;
     if (o.lanes != 0 && (o.lanes < 1 || o.lanes > 64 || (o.lanes & (o.lanes - 1)))) return CSRC_ERR_ARG;
     if (o.tile_work < 0 || o.max_rhs < 0 || o.max_rhs > csrc::kMaxRhs) return CSRC_ERR_ARG;
     if (o.persistent != 0 || o.grid != 0) return CSRC_ERR_ARG;   // reserved fields

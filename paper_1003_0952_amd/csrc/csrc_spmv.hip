@@ -1558,7 +1558,7 @@ template <class VT> struct PullWaves { static constexpr int value = 8; };
 template <> struct PullWaves<F64T> { static constexpr int value = 6; };
 
 template <class VT, class YT, int G>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PullWaves<VT>::value))) void k_owner_pull(PlanDev P, const int32_t *__restrict__ ia,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PullWaves<VT>::value))) void k_owner_pull(PlanDev P, const int32_t *__restrict__ ia,
                                                     const int32_t *__restrict__ ja,
                                                     const typename VT::V *__restrict__ ad,
                                                     const typename VT::V *__restrict__ al,
@@ -1576,7 +1576,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PullWaves<V
 // (blockIdx mod 8) walk range x with a stride, so neighbouring tiles of one
 // matrix share that XCD's L2.  The grid is a multiple of 8.
 template <class VT, class YT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PullWaves<VT>::value))) void k_batch_pull(const MatDev *__restrict__ mats, const int2 *__restrict__ items,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PullWaves<VT>::value))) void k_batch_pull(const MatDev *__restrict__ mats, const int2 *__restrict__ items,
                                                     const int32_t *__restrict__ xbeg, int transpose)
 {
     extern __shared__ __align__(16) unsigned char lds[];

@@ -37,10 +37,9 @@ PLAIN = 9        # ... or the plain kernel, which runs every matrix
 # Batched products (one persistent launch over many matrices): tile form,
 # work item size and threads per workgroup, timed on the whole batch.
 BATCH_CANDIDATES = [
-    {"variant": "owner", "tile_work": 4096, "block": 256},
     {"variant": "owner", "tile_work": 4096, "block": 512},
-    {"variant": "owner", "tile_work": 8192, "block": 512},
     {"variant": "owner", "tile_work": 16384, "block": 512},
+    {"variant": "owner", "tile_work": 32768, "block": 1024},
     {"variant": "private", "tile_work": 16384, "block": 512},
 ]
 
