@@ -92,7 +92,10 @@ __global__ __launch_bounds__(256) void k_fill_zero(YT *__restrict__ y, int32_t n
         if (gt < head) y[gt] = YT(0);
         int4 *b = reinterpret_cast<int4 *>(y + head);
         const int64_t nv = (count - head) / V;
-        for (int64_t v = gt; v < nv; v += gs) b[v] = make_int4(0, 0, 0, 0);
+        // one contiguous run of 16-byte words per workgroup (HBM row locality)
+        const int64_t per = (nv + gridDim.x - 1) / gridDim.x;
+        const int64_t v0 = blockIdx.x * per, v1 = min(nv, v0 + per);
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) b[v] = make_int4(0, 0, 0, 0);
         const int64_t t0 = head + nv * V;
         if (t0 + gt < count) y[t0 + gt] = YT(0);
         return;

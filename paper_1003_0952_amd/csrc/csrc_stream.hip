@@ -12,24 +12,37 @@ namespace csrc {
 
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
+// Workgroup b of the grid handles one contiguous run of the `count`
+// 16-byte words: [b * per, min(count, (b + 1) * per)).  A contiguous run per
+// workgroup reads about a seventh faster on this device than a grid-stride
+// walk over the same bytes (HBM row locality), so the probes measure that.
+__device__ __forceinline__ void chunk_of(int64_t count, int64_t &b, int64_t &e)
+{
+    const int64_t per = (count + gridDim.x - 1) / gridDim.x;
+    b = blockIdx.x * per;
+    e = min(count, b + per);
+}
+
 // Read `count` 16-byte words with non-temporal loads, four in flight per
-// thread per step, grid-stride; each workgroup writes the xor of everything
-// it read to sink[blockIdx.x] so that no load is dead.
+// thread per step; each workgroup writes the xor of everything it read to
+// sink[blockIdx.x] so that no load is dead.
 __global__ __launch_bounds__(256) void k_stream_read(const u4v *__restrict__ src, int64_t count,
                                                      uint32_t *__restrict__ sink)
 {
     constexpr int U = 4;
-    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int B = blockDim.x;
+    int64_t b, e;
+    chunk_of(count, b, e);
+    int64_t i = b + threadIdx.x;
     u4v acc = {0u, 0u, 0u, 0u};
-    for (; i + (U - 1) * gs < count; i += U * gs) {
+    for (; i + (U - 1) * B < e; i += U * B) {
         u4v v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * gs);
+        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * B);
 #pragma unroll
         for (int u = 0; u < U; ++u) acc ^= v[u];
     }
-    for (; i < count; i += gs) acc ^= __builtin_nontemporal_load(src + i);
+    for (; i < e; i += B) acc ^= __builtin_nontemporal_load(src + i);
     uint32_t w = acc.x ^ acc.y ^ acc.z ^ acc.w;
     for (int off = 32; off > 0; off >>= 1) w ^= __shfl_xor(w, off);
     __shared__ uint32_t red[4];
@@ -42,21 +55,24 @@ __global__ __launch_bounds__(256) void k_stream_read(const u4v *__restrict__ src
     }
 }
 
-// Copy `count` 16-byte words (non-temporal loads and stores), grid-stride.
+// Copy `count` 16-byte words (non-temporal loads and stores), one contiguous
+// run per workgroup.
 __global__ __launch_bounds__(256) void k_stream_copy(const u4v *__restrict__ src, u4v *__restrict__ dst,
                                                      int64_t count)
 {
     constexpr int U = 4;
-    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (; i + (U - 1) * gs < count; i += U * gs) {
+    const int B = blockDim.x;
+    int64_t b, e;
+    chunk_of(count, b, e);
+    int64_t i = b + threadIdx.x;
+    for (; i + (U - 1) * B < e; i += U * B) {
         u4v v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * gs);
+        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + i + u * B);
 #pragma unroll
-        for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], dst + i + u * gs);
+        for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], dst + i + u * B);
     }
-    for (; i < count; i += gs) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    for (; i < e; i += B) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace csrc
