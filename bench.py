@@ -154,7 +154,7 @@ def time_products(C, torch, cp, plan, count, transpose):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha1()
-    for f in ("csrc_spmv.hip", "csrc_plan.cpp", "internal.h"):
+    for f in ("csrc_spmv.hip", "csrc_plan.cpp", "csrc_batch.cpp", "internal.h"):
         with open(os.path.join(ROOT, "paper_1003_0952_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -343,7 +343,8 @@ def bench_rect(args):
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "max_rel_err_vs_oracle": err,
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"rect{side}", args.dtype, vname, vkw),
                      "kernel": "one product = the square product's launches + k_rect_gather (or fill + k_rect_scatter)",
                      "bytes_per_launch": B1, "duration_us": round(ms / 2 * 1e3, 2)},
         "cpu_baseline": None,
@@ -515,7 +516,9 @@ def bench_batch(args):
         "hbm_ceiling": ceiling,
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"batch{BATCH_COUNT}", args.dtype, kw.get("variant", "owner"),
+                                                 {k_: v_ for k_, v_ in kw.items() if k_ != "variant"}),
                      "kernel": ("one product = k_batch_pull (one graph launch)" if kw.get("variant", "owner") == "owner"
                                 else "one product = k_batch_tiles + k_batch_merge (one graph launch)"),
                      "bytes_per_launch": B1, "duration_us": round(ms / 2 * 1e3, 2)},
@@ -549,6 +552,15 @@ def main():
                           "measured at one GPU's shard shape (see the design notes for sharding)"}))
         sys.exit(2)
 
+    if args.calibration_copy:
+        import torch
+        src = torch.ones(2**25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.workload.startswith("batch"):
         bench_batch(args)
         return
@@ -558,14 +570,6 @@ def main():
 
     import torch
     import paper_1003_0952_amd as C
-
-    if args.calibration_copy:
-        src = torch.ones(2**25, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     t_setup = time.perf_counter()
     a, x = build_workload(args.workload)

@@ -547,7 +547,10 @@ int csrc_mlp_predict_host(int32_t hidden, int32_t classes, const float *params,
  * csrc_mlp_param_count, 12 floats each for mean and scale).  *candidate is
  * the class index, i.e. the position in the candidate list the network was
  * trained on.  params == NULL returns CSRC_ERR_NO_MODEL without touching
- * *candidate: exhaustive tuning is the fallback.  Errors: ARG, NOMEM.
+ * *candidate: exhaustive tuning is the fallback, and it is the caller's --
+ * it needs the matrix on the device and timed products, which this
+ * host-only call does not have (the Python package's selector.choose times
+ * every candidate when no model is present).  Errors: ARG, NOMEM.
  */
 int csrc_select(int32_t n, const int32_t *ia, const int32_t *ja, int32_t vdtype,
                 int32_t hidden, int32_t classes, const float *params, const float *mean,
