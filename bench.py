@@ -151,13 +151,15 @@ def time_products(C, torch, cp, plan, count, transpose):
     return t0.elapsed_time(t1) / count
 
 
-def kernel_source_hash():
-    import hashlib
-    h = hashlib.sha1()
-    for f in ("csrc_spmv.hip", "csrc_plan.cpp", "csrc_batch.cpp", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1003_0952_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_source_hash(kind="single"):
+    """Hash of the kernel sources of single-vector products, or of products
+    with several right-hand sides (kind "multi"): paper_1003_0952_amd/sources.py."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_csrc_sources", os.path.join(ROOT, "paper_1003_0952_amd",
+                                                                                 "sources.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.kernel_source_hash(kind)
 
 
 def measured_traffic(workload, dtype, vname, vkw):
@@ -168,7 +170,7 @@ def measured_traffic(workload, dtype, vname, vkw):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash("multi" if workload.startswith("batch") else "single"):
         return None
     for e in d.get("entries", []):
         if e["variant"] == vname and e["options"] == vkw:

@@ -17,8 +17,8 @@ OUT = os.path.join(OUTDIR, "libcsrc.so")
 OBJDIR = os.path.join(HERE, "_build")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["csrc_host.cpp", "csrc_plan.cpp", "csrc_batch.cpp", "csrc_mlp_host.cpp", "csrc_spmv.hip", "csrc_mlp.hip",
-           "csrc_stream.hip"]
+SOURCES = ["csrc_host.cpp", "csrc_plan.cpp", "csrc_batch.cpp", "csrc_mlp_host.cpp", "csrc_spmv.hip", "csrc_pull.hip",
+           "csrc_mlp.hip", "csrc_stream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -226,6 +226,11 @@ int color_rows(int32_t n, const int32_t *ia, const int32_t *ja, int32_t criterio
                int32_t *color, int32_t *ncolors);
 // device view of a plan's tables uploaded at base (csrc_plan.cpp)
 PlanDev plan_dev_at(const csrc_plan *p, char *base, char *partials);
+// owner multi-column kernels (csrc_pull.hip): the single-matrix kernel for w
+// columns per row (4, 8, 16 or 32) and the batched kernel, by storage and
+// output type; nullptr for anything else
+const void *owner_pull_kernel(int32_t vdtype, int32_t ydtype, int w);
+const void *batch_pull_kernel(int32_t vdtype, int32_t ydtype);
 }
 
 // A batch of independent products: one PRIVATE plan per matrix, their tables
