@@ -149,10 +149,18 @@ class Selector:
 
 
 def choose(A, torch=None, mats=None, xs=None, ys=None, model=None):
-    """Candidate index for matrix A: the model's pick, else exhaustive tuning."""
+    """Candidate index for matrix A: the model's pick (the fixed choice if the
+    library cannot plan that candidate for A), else exhaustive tuning."""
     from . import api as C
     model = model if model is not None else Selector.load()
     if model is not None:
-        return model.predict(C.csrc_features(A.host_ia, A.host_ja, A.vdtype)), "learned"
+        pick = model.predict(C.csrc_features(A.host_ia, A.host_ja, A.vdtype))
+        for i in (pick, tuner.DEFAULT, tuner.FALLBACK, tuner.PLAIN):
+            v, kw = tuner.CANDIDATES[i]
+            try:
+                C.Plan(A, v, **kw)
+            except C.CsrcError:
+                continue
+            return i, "learned" if i == pick else "fixed"
     times, best = tuner.tune(torch, mats, xs, ys)
     return best, "tuned"
