@@ -232,6 +232,7 @@ extern "C" int csrc_plan_create(int32_t n, const int32_t *ia, const int32_t *ja,
                 r.ni = p->iv_ptr[t + 1] - p->iv_ptr[t];
                 r.w = r.ni ? p->iv_slot[r.e0 + r.ni - 1] + p->iv_len[r.e0 + r.ni - 1] : 0;
                 r.goff = r.ni ? p->iv_goff[r.e0] : 0;
+                r.tail = r.k1 == ia[n] && ((r.k1 - (r.k0 & ~1)) & 1);
                 for (int k = 0; k < csrc::kRecIntervals; ++k) {
                     const bool in = k < r.ni;
                     r.ivrow[k] = in ? p->iv_row[r.e0 + k] : INT32_MAX;

@@ -180,13 +180,26 @@ struct Entries {
     __amdgpu_buffer_rsrc_t rj, ra, ru;
     int kb, ke;
 
-    __device__ __forceinline__ Entries(const int32_t *ja, const V *al, const V *au, int kb_, int ke_)
+    // pad: the value ranges end on a 4-byte boundary, i.e. a bfloat16 pair
+    // that straddles ke is read whole (its second value, entry ke, is not
+    // this range's and is ignored by the caller).  Only for ranges whose
+    // entry ke exists in the arrays.
+    __device__ __forceinline__ Entries(const int32_t *ja, const V *al, const V *au, int kb_, int ke_,
+                                       bool pad = false)
         : kb(kb_), ke(ke_)
     {
         const uint32_t n = (uint32_t)max(ke_ - kb_, 0);
+        const uint32_t vb = n * (uint32_t)sizeof(V);
         rj = make_rsrc(ja + kb_, n * 4u);
-        ra = make_rsrc(al + kb_, n * (uint32_t)sizeof(V));
-        ru = make_rsrc(au + kb_, n * (uint32_t)sizeof(V));
+        ra = make_rsrc(al + kb_, pad ? (vb + 3u) & ~3u : vb);
+        ru = make_rsrc(au + kb_, pad ? (vb + 3u) & ~3u : vb);
+    }
+
+    // the two bfloat16 values of the pair at q as one raw word (low half:
+    // entry q); a word past the range reads as zero
+    __device__ __forceinline__ uint32_t w2(__amdgpu_buffer_rsrc_t r, int q) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (q - kb) * 2, 0, kAux);
     }
 
     __device__ __forceinline__ void j2(int q, int (&o)[2]) const
@@ -277,6 +290,49 @@ struct Batch {
     }
 };
 
+// A lane's share of a batch for the branch-free stream (process_batch_flat):
+// NP pairs at qb, qb + 2B, ... of E, every value array loaded.  bfloat16
+// pairs stay raw words until they are used, so the load of the next batch is
+// never waited for while the current one is processed (E must be padded).
+template <class VT, bool NT, int NP>
+struct PairBatch {
+    using A = typename VT::A;
+    static constexpr int kPairs = NP;
+    static constexpr bool kRaw = std::is_same<typename VT::V, uint16_t>::value;
+    int j[NP][2];
+    A a[kRaw ? 1 : NP][2];
+    A u[kRaw || VT::kSym ? 1 : NP][2];
+    uint32_t aw[kRaw ? NP : 1], uw[kRaw && !VT::kSym ? NP : 1];
+
+    __device__ __forceinline__ void load(int qb, const Entries<VT, NT> &E)
+    {
+        const int half = 2 * (int)blockDim.x;
+#pragma unroll
+        for (int s = 0; s < NP; ++s) {
+            const int q = qb + half * s;
+            E.j2(q, j[s]);
+            if constexpr (kRaw) {
+                aw[s] = E.w2(E.ra, q);
+                if constexpr (!VT::kSym) uw[s] = E.w2(E.ru, q);
+            } else {
+                E.al2(q, a[s]);
+                if constexpr (!VT::kSym) E.au2(q, u[s]);
+            }
+        }
+    }
+    __device__ __forceinline__ A al(int s, int e) const
+    {
+        if constexpr (kRaw) return __uint_as_float(e ? aw[s] & 0xFFFF0000u : aw[s] << 16);
+        else return a[s][e];
+    }
+    __device__ __forceinline__ A au(int s, int e) const
+    {
+        if constexpr (VT::kSym) return al(s, e);
+        else if constexpr (kRaw) return __uint_as_float(e ? uw[s] & 0xFFFF0000u : uw[s] << 16);
+        else return u[s][e];
+    }
+};
+
 struct NoHook {
     __device__ __forceinline__ void operator()() const {}
 };
@@ -313,6 +369,8 @@ __device__ __forceinline__ double dpp(double v)
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within each group of 8
+constexpr int kDppQuadFirst = 0x00;   // quad_perm [0,0,0,0]
+constexpr int kDppQuadLast = 0xFF;    // quad_perm [3,3,3,3]
 
 // Flush a lane's pair of gathered products (rows r0 <= r1 of its two
 // entries, kNoRow for none).  Consecutive lanes often hold pairs of one long
@@ -398,35 +456,107 @@ __device__ __forceinline__ void process_batch(Batch<VT, true, LOAD_AU, NT, NP> &
     }
 }
 
+// Process one batch without divergent branches: every lane issues the same
+// LDS operations, and an operation a lane must not make is sent to its own
+// dummy sum (s_dummy[lane], a value nobody reads) with a zero addend.  Used
+// by tiles that hold their own rows and window in LDS (PRIVATE), where
+// index(j) maps every column of the tile's entries to its LDS slot; entries
+// outside the tile (kNoRow) never reach index's result.  Divergent `if`s in
+// the batch cost exec-mask bookkeeping and branches on every entry; here a
+// batch is straight-line code.
+template <class VT, bool NT, int NP, class Index>
+__device__ __forceinline__ void process_batch_flat(const PairBatch<VT, NT, NP> &cur, int qb,
+                                                   const Entries<VT, NT> &E, const uint16_t *__restrict__ s_rid,
+                                                   const typename VT::A *s_x, typename VT::S *s_y,
+                                                   typename VT::S *s_dummy, Index index)
+{
+    using A = typename VT::A;
+    using S = typename VT::S;
+    const int half = 2 * (int)blockDim.x;
+    const int kb = E.kb, k1 = E.ke;
+    const int lane = (int)(threadIdx.x & 63);
+    S *const dmy = s_dummy + lane;
+    // the row-id table holds ids [0, (k1 - kb + 3) & ~1): a lane past k1
+    // reads the last pair (the first, for an empty range), then takes kNoRow
+    // (values computed first and selected, so the compiler emits no branch)
+    const int plast = max(0, ((k1 - kb + 1) & ~1) - 2);
+    const bool quad_lead = (lane & 3) == 0;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+        const int q = qb + half * s;
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(s_rid + min(q - kb, plast));
+        const uint32_t rv = q < k1 ? w : 0xFFFFFFFFu;
+        const int r0 = (int)(rv & 0xFFFF), r1 = (int)(rv >> 16);
+        const bool v0 = r0 != (int)kNoRow, v1 = r1 != (int)kNoRow;
+        // x of the entries' own rows and of their columns (LDS slots); an
+        // entry that is not the tile's reads slot 0 and adds to the dummy,
+        // whatever its value
+        const int i0 = index(cur.j[s][0]), i1 = index(cur.j[s][1]);
+        const int ix0 = v0 ? i0 : 0, ix1 = v1 ? i1 : 0;
+        const A xr0 = s_x[v0 ? r0 : 0], xr1 = s_x[v1 ? r1 : 0];
+        const A xc0 = s_x[ix0], xc1 = s_x[ix1];
+        // scatter au x_r into sum j
+        atomic_add(v0 ? &s_y[ix0] : dmy, (S)(cur.au(s, 0) * xr0));
+        atomic_add(v1 ? &s_y[ix1] : dmy, (S)(cur.au(s, 1) * xr1));
+        // row sums: the pair's two products go to their rows; when the four
+        // lanes of an aligned quad each hold a pair of one and the same row
+        // (rows do not decrease along the lanes, so the quad's first and
+        // last lane decide), the quad's first lane adds the quad's total
+        const A g0 = cur.al(s, 0) * xc0, g1 = cur.al(s, 1) * xc1;
+        const bool one = (r0 == r1) & v0;
+        const int key = one ? r0 : -1 - lane;
+        const bool quad = dpp<kDppQuadFirst>(key) == dpp<kDppQuadLast>(key);
+        const A v = g0 + g1;
+        A vq = v + dpp<kDppXor1>(v);
+        vq = vq + dpp<kDppXor2>(vq);
+        const bool ta = (quad ? quad_lead : true) & v0;
+        const A va = quad ? vq : (one ? v : g0);
+        atomic_add(ta ? &s_y[r0] : dmy, (S)va);
+        const bool tb = !one & v1;
+        atomic_add(tb ? &s_y[r1] : dmy, (S)g1);
+    }
+}
+
 // Stream entries [kb, k1) of E (kb = k0 rounded down to even).  `cur` holds
 // the first batch, issued by the caller before its staging; each batch is
-// processed while the next one loads.  The two batches alternate roles (the
-// loop is unrolled by two), so no batch is copied between registers.  The
-// batch loop runs the same number of times in every lane (lanes past k1 see
-// only kNoRow), so after_first() is called once, by all lanes together,
-// after the first batch.
-template <class VT, bool LOAD_AU, bool NT, int NP, class NeedAu, class Ent, class Flush, class Hook = NoHook>
-__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT, NP> &cur, const Entries<VT, NT> &E,
-                                           const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
-                                           NeedAu need_au, Ent ent, Flush flush, Hook after_first = Hook())
+// processed (proc(batch, q)) while the next one loads.  The two batches
+// alternate roles (the loop is unrolled by two), so no batch is copied
+// between registers.  The batch loop runs the same number of times in every
+// lane (lanes past k1 see only kNoRow), so after_first() is called once, by
+// all lanes together, after the first batch.
+template <class Bt, class Ent, class Proc, class Hook = NoHook>
+__device__ __forceinline__ void stream_batches(Bt &cur, const Ent &E, Proc proc, Hook after_first = Hook())
 {
-    const int step = NP * 2 * (int)blockDim.x;
+    const int step = Bt::kPairs * 2 * (int)blockDim.x;
     const int kb = E.kb, k1 = E.ke;
-    Batch<VT, true, LOAD_AU, NT, NP> nxt;
+    Bt nxt;
     int base = kb;
     for (;;) {
         const int qa = base + 2 * (int)threadIdx.x;
         if (base + step < k1) nxt.load(qa + step, E);
-        process_batch<VT, LOAD_AU, NT>(cur, qa, E, s_rid, s_x, need_au, ent, flush);
+        proc(cur, qa);
         if (base == kb) after_first();
         base += step;
         if (base >= k1) break;
         const int qc = base + 2 * (int)threadIdx.x;
         if (base + step < k1) cur.load(qc + step, E);
-        process_batch<VT, LOAD_AU, NT>(nxt, qc, E, s_rid, s_x, need_au, ent, flush);
+        proc(nxt, qc);
         base += step;
         if (base >= k1) break;
     }
+}
+
+template <class VT, bool LOAD_AU, bool NT, int NP, class NeedAu, class Ent, class Flush, class Hook = NoHook>
+__device__ __forceinline__ void own_stream(Batch<VT, true, LOAD_AU, NT, NP> &cur, const Entries<VT, NT> &E,
+                                           const uint16_t *__restrict__ s_rid, const typename VT::A *s_x,
+                                           NeedAu need_au, Ent ent, Flush flush, Hook after_first = Hook())
+{
+    stream_batches(
+        cur, E,
+        [&](Batch<VT, true, LOAD_AU, NT, NP> &b, int q) {
+            process_batch<VT, LOAD_AU, NT>(b, q, E, s_rid, s_x, need_au, ent, flush);
+        },
+        after_first);
 }
 
 // Stage a tile's own rows: s_x[i] = x_i and s_y[i] = ad_i x_i (the diagonal
@@ -510,6 +640,7 @@ template <class VT, int S>
 struct NextTile {
     using A = typename VT::A;
     int r0, T, k0, k1, kb, e0, NI, W;
+    bool tail;
     int64_t goff;
     i8v rrow, rslot;          // the record's first intervals (uniform)
     A xr[S], dr[S];
@@ -534,6 +665,7 @@ struct NextTile {
         e0 = R->e0;
         NI = R->ni;
         W = R->w;
+        tail = R->tail != 0;
         goff = R->goff;
         rrow = *reinterpret_cast<const i8v *>(R->ivrow);
         rslot = *reinterpret_cast<const i8v *>(R->ivslot);
@@ -678,6 +810,21 @@ struct WindowMap {
         const int k = upper_index(s_ivrow, n, j);
         return s_ivslot[k] + (j - s_ivrow[k]);
     }
+
+    // LDS index of column j in a tile of T rows from r0 whose window slots
+    // follow its rows: j - r0 for an own row, T + slot(j) below.  The own
+    // range is one more interval start of the compare chain.
+    __device__ __forceinline__ int local(int j, int r0, int T) const
+    {
+        if (NC < kRegIntervals || n <= kRegIntervals) {
+            int o = off[0] + T;
+#pragma unroll
+            for (int k = 1; k < NC; ++k) o = j >= row[k] ? off[k] + T : o;
+            o = j >= r0 ? -r0 : o;
+            return j + o;
+        }
+        return j >= r0 ? j - r0 : T + slot(j);
+    }
 };
 
 // Local buffers of Sec. 3.1 kept in LDS: a tile of rows [r0, r1) accumulates
@@ -700,10 +847,11 @@ constexpr int kPrivatePairs = 2;
 
 constexpr int kMergePass = 0, kMergeAtomic = 1, kMergeColor = 2;
 
+
 // NC: the plan's largest number of window intervals of one tile is at most
 // NC (2, 4 or kRegIntervals): the window lookup makes NC - 1 compares.
-template <class VT, class YT, int MODE, int NC = kRegIntervals>
-__global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__restrict__ tlist,
+template <class VT, class YT, int MODE, int NC>
+__device__ __forceinline__ void private_tile(PlanDev P, const int32_t *__restrict__ tlist,
                                                  const int32_t *__restrict__ ia,
                                                  const int32_t *__restrict__ ja,
                                                  const typename VT::V *__restrict__ ad,
@@ -720,8 +868,9 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__res
     A *s_x = reinterpret_cast<A *>(lds);
     S *s_y = reinterpret_cast<S *>(lds + align16((int64_t)smax * sizeof(A)));
     uint16_t *s_rid = reinterpret_cast<uint16_t *>(lds + lds_xs(smax, sizeof(A)));
-    int32_t *s_ivrow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(s_rid) +
-                                                   align16(((int64_t)emax + 4) * 2));
+    // one dummy sum per lane (process_batch_flat), then the interval list
+    S *s_dummy = reinterpret_cast<S *>(reinterpret_cast<unsigned char *>(s_rid) + align16(((int64_t)emax + 4) * 2));
+    int32_t *s_ivrow = reinterpret_cast<int32_t *>(s_dummy + kDummySums);
 
     const int tid = threadIdx.x, B = blockDim.x;
     const int b = xcd_tile(blockIdx.x, gridDim.x);
@@ -730,8 +879,13 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__res
     nt.issue(P, t, ia, ad, x);
     A *s_xw = s_x + nt.T;
     S *s_w = s_y + nt.T;
-    const Entries<VT, true> E(ja, al, au, nt.kb, nt.k1);
-    Batch<VT, true, true, true, kPrivatePairs> first;
+    // The value ranges are read as padded pairs (Entries).  The one tile
+    // whose range ends in a bfloat16 pair past the last stored entry of the
+    // matrix (tail) streams all but that entry and adds its two products
+    // itself after the stream.
+    const Entries<VT, true> E(ja, al, au, nt.kb, nt.tail ? nt.k1 - 1 : nt.k1, true);
+    const bool tail = nt.tail && nt.k1 - 1 >= nt.k0;
+    PairBatch<VT, true, kPrivatePairs> first;
     first.load(nt.kb + 2 * tid, E);
     nt.window(x);
     nt.stage(ia, ad, x, s_x, s_y, s_xw, s_w, s_rid, s_ivrow);
@@ -741,13 +895,16 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__res
 
     WindowMap<NC> wm;
     wm.init(nt, s_ivrow);
-    auto ent = [&, wm](int j, A w) -> A {
-        const int idx = j >= r0 ? j - r0 : T + wm.slot(j);
-        atomic_add(&s_y[idx], w);
-        return s_x[idx];
-    };
-    auto flush = [&](int r, A v) { atomic_add(&s_y[r], v); };
-    own_stream<VT, true, true>(first, E, s_rid, s_x, [](int) { return true; }, ent, flush);
+    auto index = [&, wm](int j) -> int { return wm.local(j, r0, T); };
+    stream_batches(first, E, [&](PairBatch<VT, true, kPrivatePairs> &bt, int q) {
+        process_batch_flat<VT, true>(bt, q, E, s_rid, s_x, s_y, s_dummy, index);
+    });
+    if (tail && tid == 0) {
+        const int q = nt.k1 - 1;
+        const int rr = s_rid[q - nt.kb], idx = index(ja[q]);
+        atomic_add(&s_y[idx], (S)((A)ldv(au, q) * s_x[rr]));
+        atomic_add(&s_y[rr], (S)((A)ldv(al, q) * s_x[idx]));
+    }
     __syncthreads();
 
     if (MODE == kMergeAtomic) {
@@ -773,6 +930,19 @@ __global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__res
         A *part = reinterpret_cast<A *>(P.partials) + nt.goff;
         for (int sl = tid; sl < W; sl += B) part[sl] = (A)s_w[sl];
     }
+}
+
+template <class VT, class YT, int MODE, int NC = kRegIntervals>
+__global__ __launch_bounds__(512) void k_private(PlanDev P, const int32_t *__restrict__ tlist,
+                                                 const int32_t *__restrict__ ia,
+                                                 const int32_t *__restrict__ ja,
+                                                 const typename VT::V *__restrict__ ad,
+                                                 const typename VT::V *__restrict__ al,
+                                                 const typename VT::V *__restrict__ au,
+                                                 const typename VT::X *__restrict__ x,
+                                                 YT *__restrict__ y, int smax, int emax)
+{
+    private_tile<VT, YT, MODE, NC>(P, tlist, ia, ja, ad, al, au, x, y, smax, emax);
 }
 
 // ------------------------------------------------- PRIVATE, both products

@@ -32,14 +32,15 @@ constexpr int kPullEntries = 16384;   // stored entries per pull chunk (OWNER)
 // aligned (lds_xs); row ids of a block's entries are uint16, padded by 4.
 //   PRIVATE: x of own rows then window slots, sums of own rows then window
 //            slots (each sized by the largest rows + slots of one tile, smax);
-//            row ids; window interval starts and slots
+//            row ids; one dummy sum per lane; window interval starts and slots
 //   OWNER:   x of own rows and of pulled rows; sums of own rows; row ids
 //   ATOMIC:  x, sums of own rows; row ids
 constexpr int kSumBytes = 8;
 constexpr int64_t lds_xs(int64_t n, int acc) { return align16(n * acc) + align16(n * kSumBytes); }
+constexpr int kDummySums = 64;   // PRIVATE: one FP64 sum per lane that takes masked-off adds
 inline int64_t lds_private(int64_t smax, int64_t emax, int64_t ivmax, int acc)
 {
-    return lds_xs(smax, acc) + align16((emax + 4) * 2) + 2 * ivmax * 4;
+    return lds_xs(smax, acc) + align16((emax + 4) * 2) + kDummySums * kSumBytes + 2 * ivmax * 4;
 }
 // PRIVATE producing A x and A^T x together: the sums of both products
 inline int64_t lds_private_pair(int64_t smax, int64_t emax, int64_t ivmax, int acc)
@@ -113,7 +114,9 @@ struct MergeSeg {
 constexpr int kRecIntervals = 8;
 struct TileRec {
     int32_t r0, r1, k0, k1;
-    int32_t e0, ni, w, pad0;
+    int32_t e0, ni, w;
+    int32_t tail;   // the tile's entries end at the matrix's last one, an odd number of entries after
+                    // k0 rounded down to even (a bfloat16 pair read there would reach past the array)
     int64_t goff;
     int32_t pad1[6];
     int32_t ivrow[kRecIntervals];

@@ -172,3 +172,57 @@ def test_atomic_merge_fp64_output_recovers_accuracy(transpose):
           f"FP64 y max {errs['f64'][0]:.3e} rms {errs['f64'][1]:.3e}")
     assert errs["f64"][0] * 4 <= errs["f32"][0]
     assert errs["f64"][1] * 4 <= errs["f32"][1]
+
+
+def _odd_tail_matrix(kind="int"):
+    """A banded pattern on 2000 rows, then 7 rows with no stored entries below
+    the diagonal, with an odd number of stored (lower) entries: the tile that
+    holds the last entry reads an odd count from its even start, and the
+    tiles of the trailing rows have no entries at all."""
+    from synth import patterns as P
+    from synth.values import fill_values, vector
+    b = P.banded(2000, 5, 0.7, 21)
+    rows = b.rows()
+    lo = rows > b.col
+    li, lj = rows[lo], b.col[lo].astype(np.int64)
+    if len(li) % 2 == 0:
+        li, lj = li[:-1], lj[:-1]
+    a = P._from_lower_pairs(2007, li, lj, "banded_tail")
+    fill_values(a, 22, kind)
+    return a, vector(a, 23, kind)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_odd_tail_entry_is_counted_once(dtype):
+    """The PRIVATE tile kernel reads value pairs, and a bfloat16 pair that
+    straddles the end of the last tile's range would reach past the arrays;
+    that tile streams all but its last entry and adds that entry's two
+    products itself.  Integer data, bit-exact against the oracle, for one
+    row per tile (trailing tiles with no entries), small and default tiles,
+    both products and every way the tile sums reach y."""
+    import torch
+    import paper_1003_0952_amd as C
+    a, x = _odd_tail_matrix()
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    k = len(host["ja"])
+    assert k % 2 == 1 and host["ia"][a.n - 7] == k     # odd count; the last 7 rows store nothing
+    ydt = "f64" if dtype == "f64" else "f32"
+    A = C.Matrix(host, dtype)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", A.xdtype)
+    for tw in (1, 64, 1000, 0):
+        for kw in ({"atomic_merge": 1}, {}, {"variant": "tile_color"}):
+            kw = dict(kw)
+            variant = kw.pop("variant", "private")
+            plan = C.Plan(A, variant, tile_work=tw, ydtype=ydt, **kw)
+            tiles = plan.export(0)
+            last = int(np.searchsorted(tiles, a.n - 7, side="right")) - 1
+            if tw == 1:
+                assert tiles[-2] == a.n - 1 and last < len(tiles) - 2   # empty tiles at the end
+            for transpose in (False, True):
+                y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+                (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
+                torch.cuda.synchronize()
+                ref = (R.spmv_t if transpose else R.spmv)(c, x)
+                got = y.cpu().numpy().astype(np.float64)
+                assert np.array_equal(got, ref), (dtype, tw, variant, kw, transpose)
