@@ -241,7 +241,7 @@ def train_cmd(args):
            "train_samples": len(train_r), "heldout_samples": len(test_r), "heldout_ranges": args.heldout,
            "samples": "one per (matrix, storage type); features of csrc_features for that storage type",
            "training_rows": int(len(y)), "max_weight": args.max_weight,
-           "steps": args.steps,
+           "steps": args.steps, "seed": args.seed,
            "train_seconds": round(time.time() - t0, 2), "loss_first": hist[0], "loss_last": hist[-1],
            "label_histogram": np.bincount([r["best"] for r in train_r], minlength=K).tolist(),
            "candidates": [T.candidate_name(i) for i in range(K)], "default": T.candidate_name(T.DEFAULT),
