@@ -226,3 +226,37 @@ def test_odd_tail_entry_is_counted_once(dtype):
                 ref = (R.spmv_t if transpose else R.spmv)(c, x)
                 got = y.cpu().numpy().astype(np.float64)
                 assert np.array_equal(got, ref), (dtype, tw, variant, kw, transpose)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_odd_tail_entry_every_variant(dtype):
+    """The same odd-count matrix through the other tile kernels (atomic scatter,
+    owner, row colours, plain) and through the fused pair product: their
+    bfloat16 pair that straddles a tile's end takes its first value from a
+    2-byte load.  Integer data, bit-exact."""
+    import torch
+    import paper_1003_0952_amd as C
+    a, x = _odd_tail_matrix()
+    c = oracle_csrc(a)
+    host = C.csrc_from_csr(a.n, a.rowptr, a.col, a.val)
+    ydt = "f64" if dtype == "f64" else "f32"
+    A = C.Matrix(host, dtype)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", A.xdtype)
+    ref = R.spmv(c, x)
+    ref_t = R.spmv_t(c, x)
+    for variant, kw in (("atomic", {"tile_work": 64}), ("atomic", {}), ("owner", {"tile_work": 64}),
+                        ("owner", {}), ("color", {}), ("plain", {})):
+        plan = C.Plan(A, variant, ydtype=ydt, **kw)
+        for transpose, want in ((False, ref), (True, ref_t)):
+            y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+            (C.csrc_spmv_t if transpose else C.csrc_spmv)(A, plan, xt, y)
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy().astype(np.float64), want), (dtype, variant, kw, transpose)
+    for tw in (1, 64, 0):
+        plan = C.Plan(A, "private", tile_work=tw, ydtype=ydt, atomic_merge=1)
+        y = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+        yt = torch.full((A.n,), float("nan"), dtype=plan.ytorch, device="cuda")
+        C.csrc_spmv_pair(A, plan, xt, y, yt)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), ref), (dtype, "pair", tw)
+        assert np.array_equal(yt.cpu().numpy().astype(np.float64), ref_t), (dtype, "pair T", tw)
