@@ -1,6 +1,6 @@
 """Exhaustive autotuner: time every candidate (variant x tile shape) on a
 matrix and keep the fastest.  It is the learned selector's fallback and the
-judge of its regret.
+yardstick of its regret.
 
 Timing protocol: HIP events on the current stream around `reps` products
 after `warmup` products; the median of `runs` such means.  Matrices larger
